@@ -1,0 +1,186 @@
+/*
+ * vcipher.h -- C ABI of the MI355X (gfx950) implementation of the
+ * diffusion-free per-frame video cipher of arXiv 2505.07158, "Real-Time
+ * Bit-Level Encryption of Full High-Definition Video Without Diffusion".
+ *
+ * One call of encrypt_frames runs, for every frame, the whole per-frame path
+ * of the paper on the GPU:
+ *   1. the frame hash H, the xor of the SHA-256 digests of n contiguous
+ *      sub-frames (Sec. II-A; Alg. 1, Alg. 2);
+ *   2. reconstruction of the LHCS_m initial condition from the stream's
+ *      chain state and H, then 2n iterations of the hyperchaotic Lorenz
+ *      system of Eq. 1 (Sec. II-A; Alg. 1);
+ *   3. the n worker LHCS pairs that turn those iterates into shift
+ *      distances D and keystream bytes B (Sec. II-B; Alg. 2);
+ *   4. bit-level circular row shifts (Eq. 2, Alg. 4) and column shifts
+ *      (Eq. 3, Alg. 5) fused with one XOR against B (Alg. 6), i.e. Algs. 3-7
+ *      in one pass.
+ * decrypt_frames runs steps 2-4 with the exact inverse of step 4 (Sec. II-D
+ * states that decryption inverts encryption).
+ *
+ * Conventions for every function below:
+ *  - Return value: VC_OK (0) or a negative vc_status.  No function throws,
+ *    aborts or prints.
+ *  - Frames are uint8, h rows x w columns x 3 channels, row-major with
+ *    interleaved channels (L = 3*w*h bytes, byte (i*w + j)*3 + c), resident
+ *    in device memory of the context's GPU.  The caller owns every frame,
+ *    output and hash buffer and keeps them alive until the work completes.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    GPU work is enqueued asynchronously on it; host-side validation happens
+ *    before anything is enqueued, so a call that fails enqueues nothing and
+ *    leaves the chain states untouched.
+ *  - Calls on one context are serialised internally (a mutex); chain-state
+ *    updates happen in call order.  Work of one context must stay on one
+ *    stream, or the caller orders the streams.
+ *  - Protocol readings where the paper is silent (integrator, step, byte
+ *    order, partitions, layouts) are frozen as protocol version 1; see
+ *    vc_protocol_version.
+ */
+#ifndef VCIPHER_H
+#define VCIPHER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VC_OK = 0,
+    VC_EINVAL = -1,      /* bad argument, shape, key, alignment or aliasing  */
+    VC_ENOMEM = -2,      /* a frame does not fit the context's scratch, or an
+                            allocation failed                               */
+    VC_EDEVICE = -3,     /* a HIP runtime call failed                        */
+    VC_EORDER = -4,      /* frames of a stream out of sequence               */
+    VC_ENONFINITE = -5,  /* an LHCS trajectory left the finite range
+                            (reported by cipher_status)                      */
+    VC_EBUSY = -6        /* reserved                                         */
+} vc_status;
+
+/* The user key of Alg. 1 (Require): initial conditions x0, y0, z0, w0 and
+ * the control parameter gamma of Eq. 1 (hyperchaotic for
+ * -1.52 <= gamma <= -0.06, Sec. II-A), plus n, the worker count of Alg. 2,
+ * which the decryptor must match (Sec. V).  1 <= n <= 1024. */
+typedef struct {
+    double x0, y0, z0, w0;
+    double gamma;
+    uint32_t n;
+} vc_key;
+
+/* Shape and position of one frame.  c must be 3; w, h >= 1; w <= 65535,
+ * h <= 65535; n <= 3*w*h.  `stream` selects a chain (0 <= stream <
+ * max_streams of cipher_init); `seq` must equal the stream's next sequence
+ * number (0 after cipher_init or cipher_stream_reset), and frames of one
+ * stream inside a call appear in increasing seq order. */
+typedef struct {
+    uint32_t w, h, c;
+    uint32_t stream;
+    uint64_t seq;
+} vc_shape;
+
+/* Opaque context: device-resident chain states, scratch for IR, D and B,
+ * descriptor staging. */
+typedef struct vc_cipher vc_cipher;
+
+/* Protocol version of the readings this library implements (1). */
+uint32_t vc_protocol_version(void);
+
+/* Static description of a status code. Never NULL. */
+const char *vc_strerror(int status);
+
+/* Derive x0..w0 from 32 key bytes: bytes 8k..8k+7 give variable k, integer
+ * part = (big-endian u16 of the first two bytes) mod 32, fraction = the
+ * big-endian u48 of the next six bytes times 2^-48 (exact).  gamma and n are
+ * copied.  Host only.  VC_EINVAL on NULL pointers, gamma outside
+ * [-1.52, -0.06] or n outside [1, 1024]. */
+int vc_key_from_bytes(const uint8_t key32[32], double gamma, uint32_t n, vc_key *out);
+
+/* Create a context on the current HIP device.  max_streams >= 1 chains are
+ * set to the key.  scratch_bytes sizes the device scratch for IR, D and B
+ * (0 = 2 GiB); larger batches are processed in chunks that fit.  VC_EINVAL
+ * for a non-finite x0..w0, gamma outside [-1.52, -0.06], n outside
+ * [1, 1024], max_streams == 0 or out == NULL; VC_ENOMEM / VC_EDEVICE on
+ * allocation or runtime failure.  *out is NULL on error. */
+int cipher_init(const vc_key *key, uint32_t max_streams, size_t scratch_bytes, vc_cipher **out);
+
+/* Release every resource of the context (synchronises its device first).
+ * NULL is a no-op. */
+void cipher_destroy(vc_cipher *ctx);
+
+/* Encrypt `count` frames.  frames[f] (device, L bytes) is the plaintext,
+ * out[f] (device, L bytes) receives the ciphertext, hashes (device,
+ * count*32 bytes) receives each frame's H in FIPS 180-4 digest byte order;
+ * the receiver needs H to decrypt (Sec. V: hashes travel with the frames).
+ * out[f] must not overlap frames[f] (the permutation is a gather).
+ * Errors: VC_EINVAL (shape, NULL, overlap), VC_EORDER (seq), VC_ENOMEM
+ * (frame larger than the scratch), VC_EDEVICE. */
+int encrypt_frames(vc_cipher *ctx, size_t count, const uint8_t *const *frames,
+                   const vc_shape *shapes, uint8_t *hashes, uint8_t *const *out,
+                   void *stream);
+
+/* Decrypt `count` frames with the sender's hashes (device, count*32 bytes).
+ * frames[f] is ciphertext, out[f] receives the plaintext.  Same errors and
+ * ordering rules as encrypt_frames. */
+int decrypt_frames(vc_cipher *ctx, size_t count, const uint8_t *const *frames,
+                   const vc_shape *shapes, const uint8_t *hashes,
+                   uint8_t *const *out, void *stream);
+
+/* Frame hash H of Sec. II-A for each frame (n sub-frames of the context's
+ * key), without encrypting and without touching chain states. Only w, h, c
+ * of shapes are read. */
+int vc_hash_frames(vc_cipher *ctx, size_t count, const uint8_t *const *frames,
+                   const vc_shape *shapes, uint8_t *hashes, void *stream);
+
+/* Set a stream's chain back to the key (next seq 0).  Enqueued on the
+ * context's last-used stream; synchronous with respect to the host. */
+int cipher_stream_reset(vc_cipher *ctx, uint32_t stream);
+
+/* Read / write a stream's chain state: the four LHCS_m values that seed the
+ * next frame (x_2n..w_2n of the previous frame, Sec. II-A) and the next
+ * sequence number.  Both synchronise the device.  set_state rejects
+ * non-finite values (VC_EINVAL). */
+int cipher_stream_get_state(vc_cipher *ctx, uint32_t stream, double st[4], uint64_t *next_seq);
+int cipher_stream_set_state(vc_cipher *ctx, uint32_t stream, const double st[4], uint64_t next_seq);
+
+/* Synchronise `stream` and report device-side errors raised since the last
+ * call: VC_ENONFINITE if an LHCS trajectory became non-finite.  Clears the
+ * flag. */
+int cipher_status(vc_cipher *ctx, void *stream);
+
+/* Per-kernel timing with HIP events recorded on the launch stream around
+ * every kernel launch.  Kernel ids: 0 sha256_subframes, 1 lhcs_chain,
+ * 2 lhcs_keygen, 3 confuse_xor_enc, 4 confuse_xor_dec.  vc_profile_read
+ * synchronises pending events and returns the summed milliseconds and the
+ * launch count since profiling was enabled (or last reset). */
+int vc_profile_enable(vc_cipher *ctx, int enable);
+int vc_profile_read(vc_cipher *ctx, int kernel_id, double *total_ms, uint64_t *launches);
+int vc_profile_reset(vc_cipher *ctx);
+const char *vc_kernel_name(int kernel_id);
+
+/* Strip width (pixels: 4, 8, 16, 32 or 64; 0 = automatic) and
+ * threads per workgroup (256, 512 or 1024; 0 = automatic) of the
+ * confusion kernels, and whether workgroups are mapped so that all strips
+ * of one frame run on one XCD.  Tuning never changes output bytes. */
+int vc_set_tuning(vc_cipher *ctx, uint32_t strip_width, uint32_t threads, int xcd_map);
+
+/* Testing entry point: run the confusion + XOR kernels (decrypt = 0) or
+ * their inverse (decrypt = 1) on caller-supplied distances D[f] (device,
+ * 3h+3w uint16) and keystream B[f] (device, L bytes), with no hash or key
+ * schedule.  Same kernels as encrypt_frames / decrypt_frames. */
+int vc_debug_confuse(vc_cipher *ctx, int decrypt, size_t count, const uint8_t *const *in,
+                     const vc_shape *shapes, const uint16_t *const *D,
+                     const uint8_t *const *B, uint8_t *const *out, void *stream);
+
+/* Testing entry point: run the key schedule (steps 2 and 3) for frames with
+ * the given hashes, advancing the chains as decrypt_frames would, and write
+ * each frame's LHCS_m iterates IR[f] (device, 2n*4 doubles: x,y,z,w of
+ * iterations 1..2n), distances D[f] and keystream B[f]. */
+int vc_debug_keysched(vc_cipher *ctx, size_t count, const vc_shape *shapes,
+                      const uint8_t *hashes, double *const *IR, uint16_t *const *D,
+                      uint8_t *const *B, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VCIPHER_H */

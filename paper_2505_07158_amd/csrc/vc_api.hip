@@ -1,0 +1,736 @@
+// vc_api.hip -- the C ABI of libvcipher (include/vcipher.h).
+//
+// Host side of the path: argument validation, per-stream sequence checks,
+// descriptor packing (one pinned staging buffer per call, copied to the
+// device on the caller's stream), scratch planning (frames are processed in
+// chunks whose IR, D and B fit the context's scratch), and the launch
+// sequence per chunk:
+//   encrypt: sha256_subframes (all frames) -> lhcs_chain -> lhcs_keygen ->
+//            confuse_xor_enc (one launch per frame shape)
+//   decrypt: lhcs_chain -> lhcs_keygen -> confuse_xor_dec
+// All of it is enqueued asynchronously on the caller's stream.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <tuple>
+#include <vector>
+
+#include "../../include/vcipher.h"
+#include "vc_internal.hpp"
+
+using namespace vc;
+
+namespace {
+
+constexpr size_t kDefaultScratch = size_t(2) << 30;
+constexpr uint32_t kMaxN = 1024;
+constexpr double kGammaLo = -1.52;
+constexpr double kGammaHi = -0.06;
+constexpr uint32_t kMaxDim = 65535;
+constexpr int kRing = 4;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+bool key_ok(const vc_key &k) {
+    return std::isfinite(k.x0) && std::isfinite(k.y0) && std::isfinite(k.z0) && std::isfinite(k.w0) &&
+           k.gamma >= kGammaLo && k.gamma <= kGammaHi && k.n >= 1 && k.n <= kMaxN;
+}
+
+struct PendingEvent {
+    int kernel;
+    hipEvent_t a, b;
+};
+
+// Restores the caller's current device on scope exit.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) { ok = false; return; }
+        if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+struct Group {  // frames [first, first + count) of the descriptor array share a shape
+    uint32_t first, count, w, h;
+    bool aligned;
+};
+
+struct Chunk {
+    uint32_t desc_begin, desc_end;
+    uint32_t run_begin, run_end;
+    std::vector<Group> groups;
+};
+
+}  // namespace
+
+struct vc_cipher {
+    vc_key key{};
+    int device = 0;
+    uint32_t max_streams = 0;
+    double *d_state = nullptr;
+    int *d_flags = nullptr;
+    std::vector<uint64_t> next_seq;
+    uint8_t *d_scratch = nullptr;
+    size_t scratch_bytes = 0;
+    uint32_t lds_limit = 65536;
+    // descriptor staging ring
+    uint8_t *h_stage[kRing] = {};
+    uint8_t *d_stage[kRing] = {};
+    size_t stage_cap[kRing] = {};
+    hipEvent_t stage_ev[kRing] = {};
+    bool stage_live[kRing] = {};
+    int ring = 0;
+    // tuning
+    uint32_t strip = 0, threads = 0;
+    int xcd_map = 1;
+    // profiling
+    bool profile = false;
+    std::vector<PendingEvent> pending;
+    std::vector<hipEvent_t> spare;
+    double acc_ms[K_COUNT] = {};
+    uint64_t acc_n[K_COUNT] = {};
+    hipStream_t last_stream = nullptr;
+    std::mutex mu;
+};
+
+namespace {
+
+int map_err(hipError_t e) {
+    if (e == hipSuccess) return VC_OK;
+    if (e == hipErrorOutOfMemory) return VC_ENOMEM;
+    return VC_EDEVICE;
+}
+
+hipEvent_t take_event(vc_cipher *ctx) {
+    if (!ctx->spare.empty()) {
+        hipEvent_t e = ctx->spare.back();
+        ctx->spare.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Launch wrapper: records a pair of events around the launch when profiling.
+template <typename F>
+hipError_t timed(vc_cipher *ctx, int kernel, hipStream_t s, F &&launch) {
+    if (!ctx->profile) return launch();
+    hipEvent_t a = take_event(ctx), b = take_event(ctx);
+    if (!a || !b) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(a, s);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, s);
+    if (e != hipSuccess) return e;
+    ctx->pending.push_back({kernel, a, b});
+    return hipSuccess;
+}
+
+hipError_t drain_profile(vc_cipher *ctx) {
+    for (auto &p : ctx->pending) {
+        hipError_t e = hipEventSynchronize(p.b);
+        if (e != hipSuccess) return e;
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, p.a, p.b);
+        if (e != hipSuccess) return e;
+        ctx->acc_ms[p.kernel] += ms;
+        ctx->acc_n[p.kernel] += 1;
+        ctx->spare.push_back(p.a);
+        ctx->spare.push_back(p.b);
+    }
+    ctx->pending.clear();
+    return hipSuccess;
+}
+
+// Pinned host + device staging for one call's descriptors.  A slot is
+// reused only after the event recorded behind the last kernel that read it.
+int stage_acquire(vc_cipher *ctx, size_t bytes, int *slot_out) {
+    const int slot = ctx->ring;
+    ctx->ring = (ctx->ring + 1) % kRing;
+    if (ctx->stage_live[slot]) {
+        if (hipEventSynchronize(ctx->stage_ev[slot]) != hipSuccess) return VC_EDEVICE;
+        ctx->stage_live[slot] = false;
+    }
+    if (ctx->stage_cap[slot] < bytes) {
+        if (ctx->h_stage[slot]) (void)hipHostFree(ctx->h_stage[slot]);
+        if (ctx->d_stage[slot]) (void)hipFree(ctx->d_stage[slot]);
+        ctx->h_stage[slot] = nullptr;
+        ctx->d_stage[slot] = nullptr;
+        ctx->stage_cap[slot] = 0;
+        const size_t cap = std::max(align_up(bytes, 4096), size_t(65536));
+        if (hipHostMalloc(reinterpret_cast<void **>(&ctx->h_stage[slot]), cap, hipHostMallocDefault) !=
+            hipSuccess)
+            return VC_ENOMEM;
+        if (hipMalloc(reinterpret_cast<void **>(&ctx->d_stage[slot]), cap) != hipSuccess) return VC_ENOMEM;
+        ctx->stage_cap[slot] = cap;
+    }
+    *slot_out = slot;
+    return VC_OK;
+}
+
+uint64_t frame_bytes(const vc_shape &s) { return 3ull * s.w * s.h; }
+
+uint64_t scratch_need(const vc_shape &s, uint32_t n) {
+    const uint64_t L = frame_bytes(s);
+    const uint64_t ND = 3ull * s.h + 3ull * s.w;
+    return align_up(L, 256) + align_up(2 * ND, 256) + align_up(64ull * n, 256);
+}
+
+bool overlaps(const uint8_t *a, uint64_t la, const uint8_t *b, uint64_t lb) {
+    return a < b + lb && b < a + la;
+}
+
+int check_shape(const vc_cipher *ctx, const vc_shape &s, int decrypt, bool uses_n) {
+    if (s.c != 3 || s.w < 1 || s.h < 1 || s.w > kMaxDim || s.h > kMaxDim) return VC_EINVAL;
+    if (uses_n && ctx->key.n > frame_bytes(s)) return VC_EINVAL;
+    if (confuse_max_strip(decrypt, s.h, ctx->lds_limit) == 0) return VC_EINVAL;
+    return VC_OK;
+}
+
+uint32_t pick_strip(const vc_cipher *ctx, int decrypt, uint32_t w, uint32_t h) {
+    const uint32_t wcap = std::max<uint32_t>(4, (w + 3) / 4 * 4);
+    if (ctx->strip) {
+        if (ctx->strip <= wcap && confuse_lds_bytes(decrypt, h, ctx->strip) <= ctx->lds_limit)
+            return ctx->strip;
+    }
+    // widest strip that leaves room for two workgroups per CU, else the
+    // widest that fits at all
+    uint32_t best = 0, fits = 0;
+    for (uint32_t wt = 4; wt <= 64 && wt <= wcap; wt *= 2) {
+        if (confuse_lds_bytes(decrypt, h, wt) <= ctx->lds_limit / 2) best = wt;
+        if (confuse_lds_bytes(decrypt, h, wt) <= ctx->lds_limit) fits = wt;
+    }
+    return best ? best : fits;
+}
+
+enum class Op { Encrypt, Decrypt, Hash, DebugConfuse, DebugKeysched };
+
+struct CallArgs {
+    Op op;
+    size_t count;
+    const uint8_t *const *in;
+    const vc_shape *shapes;
+    const uint8_t *hashes;       // H in (decrypt, keysched)
+    uint8_t *hashes_out;         // H out (encrypt, hash)
+    uint8_t *const *out;
+    const uint16_t *const *dbgD;  // debug confuse inputs
+    const uint8_t *const *dbgB;
+    double *const *kIR;           // debug keysched outputs
+    uint16_t *const *kD;
+    uint8_t *const *kB;
+    int decrypt;                  // for DebugConfuse
+    hipStream_t stream;
+};
+
+int run_call(vc_cipher *ctx, const CallArgs &a) {
+    const bool uses_chain = a.op == Op::Encrypt || a.op == Op::Decrypt || a.op == Op::DebugKeysched;
+    const bool uses_scratch = a.op == Op::Encrypt || a.op == Op::Decrypt;
+    const int dec_kernel = (a.op == Op::Decrypt) || (a.op == Op::DebugConfuse && a.decrypt);
+    const uint32_t n = ctx->key.n;
+    const size_t count = a.count;
+
+    // ---- validation (nothing enqueued yet) ----
+    std::map<uint32_t, uint64_t> seq_next;
+    for (size_t f = 0; f < count; ++f) {
+        const vc_shape &s = a.shapes[f];
+        int rc = check_shape(ctx, s, dec_kernel, a.op != Op::DebugConfuse);
+        if (rc) return rc;
+        const uint64_t L = frame_bytes(s);
+        if (a.op != Op::DebugKeysched && !a.in[f]) return VC_EINVAL;
+        if ((a.op == Op::Encrypt || a.op == Op::Decrypt || a.op == Op::DebugConfuse) && !a.out[f])
+            return VC_EINVAL;
+        if ((a.op == Op::Encrypt || a.op == Op::DebugConfuse || a.op == Op::Decrypt) &&
+            overlaps(a.in[f], L, a.out[f], L))
+            return VC_EINVAL;
+        if (a.op == Op::DebugConfuse && (!a.dbgD[f] || !a.dbgB[f])) return VC_EINVAL;
+        if (a.op == Op::DebugKeysched && (!a.kIR[f] || !a.kD[f] || !a.kB[f])) return VC_EINVAL;
+        if (uses_scratch && scratch_need(s, n) > ctx->scratch_bytes) return VC_ENOMEM;
+        if (uses_chain) {
+            if (s.stream >= ctx->max_streams) return VC_EINVAL;
+            auto it = seq_next.find(s.stream);
+            const uint64_t expect = (it == seq_next.end()) ? ctx->next_seq[s.stream] : it->second;
+            if (s.seq != expect) return VC_EORDER;
+            seq_next[s.stream] = expect + 1;
+        }
+    }
+    if (count == 0) return VC_OK;
+
+    // ---- plan chunks (consecutive frames whose scratch fits) ----
+    std::vector<std::pair<size_t, size_t>> spans;  // [begin, end) in call order
+    {
+        size_t b = 0;
+        uint64_t used = 0;
+        for (size_t f = 0; f < count; ++f) {
+            const uint64_t need = uses_scratch ? scratch_need(a.shapes[f], n) : 0;
+            if (f > b && used + need > ctx->scratch_bytes) {
+                spans.push_back({b, f});
+                b = f;
+                used = 0;
+            }
+            used += need;
+        }
+        spans.push_back({b, count});
+    }
+
+    // ---- build descriptors, runs and order ----
+    std::vector<FrameDesc> desc(count);
+    std::vector<StreamRun> runs;
+    std::vector<uint32_t> order;
+    std::vector<Chunk> chunks;
+    std::vector<uint32_t> desc_of(count);
+    for (auto &sp : spans) {
+        Chunk ch;
+        ch.desc_begin = static_cast<uint32_t>(sp.first);
+        ch.desc_end = static_cast<uint32_t>(sp.second);
+        // shape groups: stable order by (w, h, aligned)
+        std::vector<size_t> idx;
+        for (size_t f = sp.first; f < sp.second; ++f) idx.push_back(f);
+        auto aligned_of = [&](size_t f) {
+            const vc_shape &s = a.shapes[f];
+            if (s.w % 4) return false;
+            const uintptr_t pin = reinterpret_cast<uintptr_t>(a.in ? a.in[f] : nullptr);
+            const uintptr_t pout = reinterpret_cast<uintptr_t>(a.out ? a.out[f] : nullptr);
+            if ((pin | pout) & 3) return false;
+            if (a.op == Op::DebugConfuse && (reinterpret_cast<uintptr_t>(a.dbgB[f]) & 3)) return false;
+            return true;
+        };
+        std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) {
+            const vc_shape &p = a.shapes[x], &q = a.shapes[y];
+            return std::make_tuple(p.w, p.h, !aligned_of(x)) < std::make_tuple(q.w, q.h, !aligned_of(y));
+        });
+        uint64_t off = 0;
+        for (size_t k = 0; k < idx.size(); ++k) {
+            const size_t f = idx[k];
+            const uint32_t di = static_cast<uint32_t>(sp.first + k);
+            desc_of[f] = di;
+            const vc_shape &s = a.shapes[f];
+            FrameDesc &d = desc[di];
+            d.in = a.in ? a.in[f] : nullptr;
+            d.out = a.out ? a.out[f] : nullptr;
+            d.w = s.w;
+            d.h = s.h;
+            d.L = frame_bytes(s);
+            d.hash = a.hashes_out ? a.hashes_out + 32 * f
+                                  : const_cast<uint8_t *>(a.hashes ? a.hashes + 32 * f : nullptr);
+            d.IR = nullptr;
+            d.D = nullptr;
+            d.B = nullptr;
+            if (uses_scratch) {
+                const uint64_t ND = 3ull * s.h + 3ull * s.w;
+                d.B = ctx->d_scratch + off;
+                off += align_up(d.L, 256);
+                d.D = reinterpret_cast<uint16_t *>(ctx->d_scratch + off);
+                off += align_up(2 * ND, 256);
+                d.IR = reinterpret_cast<double *>(ctx->d_scratch + off);
+                off += align_up(64ull * n, 256);
+            } else if (a.op == Op::DebugConfuse) {
+                d.D = const_cast<uint16_t *>(a.dbgD[f]);
+                d.B = const_cast<uint8_t *>(a.dbgB[f]);
+            } else if (a.op == Op::DebugKeysched) {
+                d.IR = a.kIR[f];
+                d.D = a.kD[f];
+                d.B = a.kB[f];
+            }
+            const bool al = aligned_of(f);
+            if (!ch.groups.empty()) {
+                Group &g = ch.groups.back();
+                if (g.w == s.w && g.h == s.h && g.aligned == al) {
+                    g.count++;
+                    continue;
+                }
+            }
+            ch.groups.push_back({di, 1, s.w, s.h, al});
+        }
+        // stream runs in call (= sequence) order
+        ch.run_begin = static_cast<uint32_t>(runs.size());
+        if (uses_chain) {
+            std::map<uint32_t, std::vector<uint32_t>> per_stream;
+            std::vector<uint32_t> stream_order;
+            for (size_t f = sp.first; f < sp.second; ++f) {
+                auto &v = per_stream[a.shapes[f].stream];
+                if (v.empty()) stream_order.push_back(a.shapes[f].stream);
+                v.push_back(desc_of[f]);
+            }
+            for (uint32_t st : stream_order) {
+                auto &v = per_stream[st];
+                runs.push_back({st, static_cast<uint32_t>(order.size()), static_cast<uint32_t>(v.size()), 0});
+                order.insert(order.end(), v.begin(), v.end());
+            }
+        }
+        ch.run_end = static_cast<uint32_t>(runs.size());
+        chunks.push_back(std::move(ch));
+    }
+
+    // ---- stage and upload ----
+    const size_t desc_bytes = align_up(sizeof(FrameDesc) * count, 256);
+    const size_t runs_bytes = align_up(sizeof(StreamRun) * std::max<size_t>(runs.size(), 1), 256);
+    const size_t order_bytes = align_up(sizeof(uint32_t) * std::max<size_t>(order.size(), 1), 256);
+    const size_t total = desc_bytes + runs_bytes + order_bytes;
+    int slot = 0;
+    int rc = stage_acquire(ctx, total, &slot);
+    if (rc) return rc;
+    uint8_t *hs = ctx->h_stage[slot];
+    std::memcpy(hs, desc.data(), sizeof(FrameDesc) * count);
+    if (!runs.empty()) std::memcpy(hs + desc_bytes, runs.data(), sizeof(StreamRun) * runs.size());
+    if (!order.empty()) std::memcpy(hs + desc_bytes + runs_bytes, order.data(), sizeof(uint32_t) * order.size());
+    const hipStream_t s = a.stream;
+    uint8_t *ds = ctx->d_stage[slot];
+    hipError_t e = hipMemcpyAsync(ds, hs, total, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return map_err(e);
+    const FrameDesc *d_desc = reinterpret_cast<const FrameDesc *>(ds);
+    const StreamRun *d_runs = reinterpret_cast<const StreamRun *>(ds + desc_bytes);
+    const uint32_t *d_order = reinterpret_cast<const uint32_t *>(ds + desc_bytes + runs_bytes);
+
+    // The sequence numbers advance as soon as work is enqueued: the chain
+    // states on the device follow stream order.
+    if (uses_chain)
+        for (auto &kv : seq_next) ctx->next_seq[kv.first] = kv.second;
+
+    ConfuseTuning tun;
+    tun.threads = ctx->threads ? ctx->threads : 512;
+    tun.xcd_map = ctx->xcd_map;
+
+    // ---- launches ----
+    if (a.op == Op::Encrypt || a.op == Op::Hash) {
+        e = timed(ctx, K_SHA, s, [&] { return launch_sha256_subframes(d_desc, static_cast<uint32_t>(count), n, s); });
+        if (e != hipSuccess) return map_err(e);
+    }
+    if (a.op != Op::Hash) {
+        for (const Chunk &ch : chunks) {
+            if (uses_chain) {
+                e = timed(ctx, K_CHAIN, s, [&] {
+                    return launch_lhcs_chain(d_desc, d_runs + ch.run_begin, d_order, ch.run_end - ch.run_begin,
+                                             ctx->d_state, n, ctx->key.gamma, ctx->d_flags, s);
+                });
+                if (e != hipSuccess) return map_err(e);
+                e = timed(ctx, K_KEYGEN, s, [&] {
+                    return launch_lhcs_keygen(d_desc + ch.desc_begin, ch.desc_end - ch.desc_begin, n,
+                                              ctx->key.gamma, ctx->d_flags, s);
+                });
+                if (e != hipSuccess) return map_err(e);
+            }
+            if (a.op == Op::DebugKeysched) continue;
+            for (const Group &g : ch.groups) {
+                tun.strip = pick_strip(ctx, dec_kernel, g.w, g.h);
+                e = timed(ctx, dec_kernel ? K_DEC : K_ENC, s, [&] {
+                    return launch_confuse(dec_kernel, d_desc, g.first, g.count, g.w, g.h, g.aligned, tun, s);
+                });
+                if (e != hipSuccess) return map_err(e);
+            }
+        }
+    }
+    e = hipEventRecord(ctx->stage_ev[slot], s);
+    if (e != hipSuccess) return map_err(e);
+    ctx->stage_live[slot] = true;
+    ctx->last_stream = s;
+    return VC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t vc_protocol_version(void) { return 1; }
+
+const char *vc_strerror(int status) {
+    switch (status) {
+    case VC_OK: return "ok";
+    case VC_EINVAL: return "invalid argument";
+    case VC_ENOMEM: return "out of memory (device scratch or allocation)";
+    case VC_EDEVICE: return "HIP runtime error";
+    case VC_EORDER: return "frame out of sequence for its stream";
+    case VC_ENONFINITE: return "LHCS trajectory became non-finite";
+    case VC_EBUSY: return "busy";
+    default: return "unknown status";
+    }
+}
+
+const char *vc_kernel_name(int kernel_id) {
+    switch (kernel_id) {
+    case K_SHA: return "sha256_subframes";
+    case K_CHAIN: return "lhcs_chain";
+    case K_KEYGEN: return "lhcs_keygen";
+    case K_ENC: return "confuse_xor_enc";
+    case K_DEC: return "confuse_xor_dec";
+    default: return "";
+    }
+}
+
+int vc_key_from_bytes(const uint8_t key32[32], double gamma, uint32_t n, vc_key *out) {
+    if (!key32 || !out) return VC_EINVAL;
+    if (!(gamma >= kGammaLo && gamma <= kGammaHi) || n < 1 || n > kMaxN) return VC_EINVAL;
+    double v[4];
+    for (int k = 0; k < 4; ++k) {
+        const uint8_t *q = key32 + 8 * k;
+        const uint32_t ip = ((uint32_t(q[0]) << 8) | q[1]) % 32u;
+        uint64_t fr = 0;
+        for (int b = 2; b < 8; ++b) fr = (fr << 8) | q[b];
+        v[k] = static_cast<double>(ip) + static_cast<double>(fr) * (1.0 / 281474976710656.0);
+    }
+    out->x0 = v[0];
+    out->y0 = v[1];
+    out->z0 = v[2];
+    out->w0 = v[3];
+    out->gamma = gamma;
+    out->n = n;
+    return VC_OK;
+}
+
+void cipher_destroy(vc_cipher *ctx) {
+    if (!ctx) return;
+    {
+        DeviceGuard g(ctx->device);
+        (void)hipDeviceSynchronize();
+        for (auto &p : ctx->pending) {
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
+        for (auto ev : ctx->spare) (void)hipEventDestroy(ev);
+        for (int k = 0; k < kRing; ++k) {
+            if (ctx->h_stage[k]) (void)hipHostFree(ctx->h_stage[k]);
+            if (ctx->d_stage[k]) (void)hipFree(ctx->d_stage[k]);
+            if (ctx->stage_ev[k]) (void)hipEventDestroy(ctx->stage_ev[k]);
+        }
+        if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
+        if (ctx->d_state) (void)hipFree(ctx->d_state);
+        if (ctx->d_flags) (void)hipFree(ctx->d_flags);
+    }
+    delete ctx;
+}
+
+int cipher_init(const vc_key *key, uint32_t max_streams, size_t scratch_bytes, vc_cipher **out) {
+    if (out) *out = nullptr;
+    if (!key || !out || max_streams == 0 || !key_ok(*key)) return VC_EINVAL;
+    vc_cipher *ctx = new (std::nothrow) vc_cipher();
+    if (!ctx) return VC_ENOMEM;
+    ctx->key = *key;
+    ctx->max_streams = max_streams;
+    ctx->scratch_bytes = scratch_bytes ? scratch_bytes : kDefaultScratch;
+    int rc = VC_OK;
+    do {
+        if (hipGetDevice(&ctx->device) != hipSuccess) { rc = VC_EDEVICE; break; }
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ctx->device) != hipSuccess) {
+            rc = VC_EDEVICE;
+            break;
+        }
+        ctx->lds_limit = static_cast<uint32_t>(lds);
+        if (confuse_configure(ctx->lds_limit) != hipSuccess) { rc = VC_EDEVICE; break; }
+        try {
+            ctx->next_seq.assign(max_streams, 0);
+        } catch (...) {
+            rc = VC_ENOMEM;
+            break;
+        }
+        hipError_t e = hipMalloc(reinterpret_cast<void **>(&ctx->d_state), sizeof(double) * 4 * max_streams);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&ctx->d_flags), 256);
+        if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&ctx->d_scratch), ctx->scratch_bytes);
+        if (e != hipSuccess) { rc = map_err(e); break; }
+        std::vector<double> st(4ull * max_streams);
+        for (uint32_t k = 0; k < max_streams; ++k) {
+            st[4 * k] = key->x0;
+            st[4 * k + 1] = key->y0;
+            st[4 * k + 2] = key->z0;
+            st[4 * k + 3] = key->w0;
+        }
+        e = hipMemcpy(ctx->d_state, st.data(), sizeof(double) * st.size(), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemset(ctx->d_flags, 0, 256);
+        for (int k = 0; k < kRing && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ctx->stage_ev[k], hipEventDisableTiming);
+        if (e != hipSuccess) { rc = map_err(e); break; }
+    } while (false);
+    if (rc != VC_OK) {
+        cipher_destroy(ctx);
+        return rc;
+    }
+    *out = ctx;
+    return VC_OK;
+}
+
+static int locked_call(vc_cipher *ctx, const CallArgs &a) {
+    if (!ctx) return VC_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return VC_EDEVICE;
+    return run_call(ctx, a);
+}
+
+int encrypt_frames(vc_cipher *ctx, size_t count, const uint8_t *const *frames, const vc_shape *shapes,
+                   uint8_t *hashes, uint8_t *const *out, void *stream) {
+    if (count && (!frames || !shapes || !hashes || !out)) return VC_EINVAL;
+    CallArgs a{};
+    a.op = Op::Encrypt;
+    a.count = count;
+    a.in = frames;
+    a.shapes = shapes;
+    a.hashes_out = hashes;
+    a.out = out;
+    a.stream = static_cast<hipStream_t>(stream);
+    return locked_call(ctx, a);
+}
+
+int decrypt_frames(vc_cipher *ctx, size_t count, const uint8_t *const *frames, const vc_shape *shapes,
+                   const uint8_t *hashes, uint8_t *const *out, void *stream) {
+    if (count && (!frames || !shapes || !hashes || !out)) return VC_EINVAL;
+    CallArgs a{};
+    a.op = Op::Decrypt;
+    a.count = count;
+    a.in = frames;
+    a.shapes = shapes;
+    a.hashes = hashes;
+    a.out = out;
+    a.stream = static_cast<hipStream_t>(stream);
+    return locked_call(ctx, a);
+}
+
+int vc_hash_frames(vc_cipher *ctx, size_t count, const uint8_t *const *frames, const vc_shape *shapes,
+                   uint8_t *hashes, void *stream) {
+    if (count && (!frames || !shapes || !hashes)) return VC_EINVAL;
+    CallArgs a{};
+    a.op = Op::Hash;
+    a.count = count;
+    a.in = frames;
+    a.shapes = shapes;
+    a.hashes_out = hashes;
+    a.stream = static_cast<hipStream_t>(stream);
+    return locked_call(ctx, a);
+}
+
+int vc_debug_confuse(vc_cipher *ctx, int decrypt, size_t count, const uint8_t *const *in, const vc_shape *shapes,
+                     const uint16_t *const *D, const uint8_t *const *B, uint8_t *const *out, void *stream) {
+    if (count && (!in || !shapes || !D || !B || !out)) return VC_EINVAL;
+    CallArgs a{};
+    a.op = Op::DebugConfuse;
+    a.decrypt = decrypt ? 1 : 0;
+    a.count = count;
+    a.in = in;
+    a.shapes = shapes;
+    a.dbgD = D;
+    a.dbgB = B;
+    a.out = out;
+    a.stream = static_cast<hipStream_t>(stream);
+    return locked_call(ctx, a);
+}
+
+int vc_debug_keysched(vc_cipher *ctx, size_t count, const vc_shape *shapes, const uint8_t *hashes,
+                      double *const *IR, uint16_t *const *D, uint8_t *const *B, void *stream) {
+    if (count && (!shapes || !hashes || !IR || !D || !B)) return VC_EINVAL;
+    CallArgs a{};
+    a.op = Op::DebugKeysched;
+    a.count = count;
+    a.shapes = shapes;
+    a.hashes = hashes;
+    a.kIR = IR;
+    a.kD = D;
+    a.kB = B;
+    a.stream = static_cast<hipStream_t>(stream);
+    return locked_call(ctx, a);
+}
+
+int cipher_stream_reset(vc_cipher *ctx, uint32_t stream) {
+    if (!ctx || stream >= ctx->max_streams) return VC_EINVAL;
+    const double st[4] = {ctx->key.x0, ctx->key.y0, ctx->key.z0, ctx->key.w0};
+    return cipher_stream_set_state(ctx, stream, st, 0);
+}
+
+int cipher_stream_get_state(vc_cipher *ctx, uint32_t stream, double st[4], uint64_t *next_seq) {
+    if (!ctx || !st || stream >= ctx->max_streams) return VC_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return VC_EDEVICE;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess)
+        e = hipMemcpy(st, ctx->d_state + 4ull * stream, 4 * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return map_err(e);
+    if (next_seq) *next_seq = ctx->next_seq[stream];
+    return VC_OK;
+}
+
+int cipher_stream_set_state(vc_cipher *ctx, uint32_t stream, const double st[4], uint64_t next_seq) {
+    if (!ctx || !st || stream >= ctx->max_streams) return VC_EINVAL;
+    for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(st[k])) return VC_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return VC_EDEVICE;
+    hipError_t e = hipDeviceSynchronize();
+    if (e == hipSuccess)
+        e = hipMemcpy(ctx->d_state + 4ull * stream, st, 4 * sizeof(double), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return map_err(e);
+    ctx->next_seq[stream] = next_seq;
+    return VC_OK;
+}
+
+int cipher_status(vc_cipher *ctx, void *stream) {
+    if (!ctx) return VC_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return VC_EDEVICE;
+    hipError_t e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    int flags = 0;
+    if (e == hipSuccess) e = hipMemcpy(&flags, ctx->d_flags, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return map_err(e);
+    if (flags) {
+        const int zero = 0;
+        e = hipMemcpy(ctx->d_flags, &zero, sizeof(int), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return map_err(e);
+        return VC_ENONFINITE;
+    }
+    return VC_OK;
+}
+
+int vc_profile_enable(vc_cipher *ctx, int enable) {
+    if (!ctx) return VC_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->profile = enable != 0;
+    return VC_OK;
+}
+
+int vc_profile_read(vc_cipher *ctx, int kernel_id, double *total_ms, uint64_t *launches) {
+    if (!ctx || kernel_id < 0 || kernel_id >= K_COUNT) return VC_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return VC_EDEVICE;
+    hipError_t e = drain_profile(ctx);
+    if (e != hipSuccess) return map_err(e);
+    if (total_ms) *total_ms = ctx->acc_ms[kernel_id];
+    if (launches) *launches = ctx->acc_n[kernel_id];
+    return VC_OK;
+}
+
+int vc_profile_reset(vc_cipher *ctx) {
+    if (!ctx) return VC_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return VC_EDEVICE;
+    hipError_t e = drain_profile(ctx);
+    for (int k = 0; k < K_COUNT; ++k) {
+        ctx->acc_ms[k] = 0;
+        ctx->acc_n[k] = 0;
+    }
+    return map_err(e);
+}
+
+int vc_set_tuning(vc_cipher *ctx, uint32_t strip_width, uint32_t threads, int xcd_map) {
+    if (!ctx) return VC_EINVAL;
+    if (strip_width && (strip_width % 4 || strip_width < 4 || strip_width > 64 ||
+                        (strip_width & (strip_width - 1))))
+        return VC_EINVAL;
+    if (threads && threads != 256 && threads != 512 && threads != 1024) return VC_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->strip = strip_width;
+    ctx->threads = threads;
+    ctx->xcd_map = xcd_map ? 1 : 0;
+    return VC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,396 @@
+// vc_confuse.hip -- bit-level confusion fused with one XOR round (Sec. II-C
+// of arXiv 2505.07158: Eq. 2 row shifts, Eq. 3 column shifts, Algs. 3-7) and
+// its exact inverse, on gfx950.
+//
+// The paper keeps an 8w x h bit matrix per channel and runs five kernels
+// (bit extraction, H-shift, V-shift, XOR, packing) with full-matrix copies
+// in between.  Here the bits never leave byte form.  For output byte
+// (i, j, c) (row i, pixel column j, channel c), with d_h = D[c*h + r] and
+// d_v = D[3h + c*w + j]:
+//     r = (i - d_v mod h) mod h,     s = (8j - d_h mod 8w) mod 8w,
+//     C[i][j][c] = bits s..s+7 of source row r, channel c  xor  B[i][j][c]
+// where "bits s..s+7" is the funnel shift of pixels s/8 and s/8+1 (mod w),
+// least significant bit first (Algs. 3 and 7).
+//
+// Tiling: a workgroup owns a full-height strip of WT pixel columns (all
+// three channels) of one frame.  A column shift stays inside the strip, and
+// a row shift maps the strip to one contiguous window of WT+1 pixels of each
+// source row, so
+//   phase 1: for every source row r and channel c, funnel-shift its window
+//            into LDS (one 16-byte global load per four output bytes),
+//   phase 2: every output row of the strip gathers its bytes from the LDS
+//            rows (i - d_v) mod h, xors B and stores C with coalesced dword
+//            accesses.
+// Decryption mirrors it: coalesced loads of C and B into LDS with the column
+// shift undone, then the row funnel shift scattered to the plaintext rows.
+// Workgroups are mapped so that all strips of one frame run on one XCD and
+// share its L2 (the row windows of neighbouring strips overlap).
+#include <algorithm>
+
+#include "vc_internal.hpp"
+
+namespace vc {
+namespace {
+
+typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+
+// x mod m for x < 2^16 and 1 <= m < 2^21: float reciprocal estimate of the
+// quotient (off by at most one) plus one correction.
+__device__ __forceinline__ uint32_t mod16(uint32_t x, uint32_t m, float inv_m) {
+    const uint32_t q = static_cast<uint32_t>(static_cast<float>(x) * inv_m);
+    int32_t r = static_cast<int32_t>(x) - static_cast<int32_t>(q * m);
+    if (r < 0) r += static_cast<int32_t>(m);
+    if (r >= static_cast<int32_t>(m)) r -= static_cast<int32_t>(m);
+    return static_cast<uint32_t>(r);
+}
+
+// Workgroup -> (frame within the launch, strip).  With xcd_map the
+// hardware's round-robin placement of consecutive workgroups over the 8 XCDs
+// is undone: XCD x (workgroups g with g % 8 == x) gets frames x, x+8, ...,
+// each frame's strips consecutively.
+__device__ __forceinline__ void map_workgroup(uint32_t g, uint32_t nstrips, int xcd_map, uint32_t &fl,
+                                              uint32_t &strip) {
+    if (xcd_map) {
+        const uint32_t x = g & 7, l = g >> 3;
+        const uint32_t slot = l / nstrips;
+        strip = l - slot * nstrips;
+        fl = slot * 8 + x;
+    } else {
+        fl = g / nstrips;
+        strip = g - fl * nstrips;
+    }
+}
+
+struct Geometry {
+    uint32_t w, h, W8, row_bytes;
+    float inv_h, inv_W8;
+};
+
+// ----------------------------------------------------------------------
+// Encryption
+// ----------------------------------------------------------------------
+template <int WT, int NT>
+__global__ __launch_bounds__(NT) void confuse_xor_enc(const FrameDesc *__restrict__ desc, uint32_t first,
+                                                      uint32_t nframes, Geometry geo, uint32_t nstrips,
+                                                      int xcd_map, int aligned) {
+    extern __shared__ __align__(16) uint8_t S[];
+    constexpr uint32_t RS = 3 * WT;            // LDS row: channel c at c*WT + k
+    constexpr uint32_t KG = WT / 4;            // 4-byte groups per (row, channel)
+    constexpr uint32_t KPL = KG < 4 ? KG : 4;  // groups per lane
+    constexpr uint32_t LPG = KG / KPL;         // lanes per (row, channel)
+
+    uint32_t fl, strip;
+    map_workgroup(blockIdx.x, nstrips, xcd_map, fl, strip);
+    if (fl >= nframes) return;
+    const FrameDesc d = desc[first + fl];
+    const uint32_t w = geo.w, h = geo.h, W8 = geo.W8, row_bytes = geo.row_bytes;
+    const uint32_t j0 = strip * WT;
+    const uint32_t wt = (w - j0 < static_cast<uint32_t>(WT)) ? w - j0 : WT;
+    const uint8_t *__restrict__ P = d.in;
+    const uint16_t *__restrict__ D = d.D;
+
+    // Phase 1: S[r][c][k] = bits (8(j0+k) - d_h(c,r)) .. +7 of row r, channel c.
+    const uint32_t items1 = h * 3 * LPG;
+    for (uint32_t it = threadIdx.x; it < items1; it += NT) {
+        const uint32_t kl = it % LPG, rc = it / LPG;
+        const uint32_t r = rc / 3, c = rc - 3 * r;
+        const uint32_t dh = mod16(D[c * h + r], W8, geo.inv_W8);
+        uint32_t s0 = 8 * j0 + W8 - dh;
+        if (s0 >= W8) s0 -= W8;
+        const uint32_t t = s0 & 7;
+        uint32_t q = (s0 >> 3) + 4 * KPL * kl;
+        if (q >= w) q -= w;
+        const uint8_t *row = P + static_cast<uint64_t>(r) * row_bytes + c;
+        uint8_t *dst = S + r * RS + c * WT + 4 * KPL * kl;
+#pragma unroll
+        for (uint32_t u = 0; u < KPL; ++u) {
+            uint32_t X, b4;
+            if (aligned && q + 4 < w) {
+                // pixels q..q+4 of channel c: bytes 3q+c+{0,3,6,9,12}
+                const uintptr_t sa = reinterpret_cast<uintptr_t>(row + 3 * q);
+                const uint32_t sh = static_cast<uint32_t>(sa & 3);
+                const u32x4_a4 v = *reinterpret_cast<const u32x4_a4 *>(sa - sh);
+                const uint32_t e0 = __builtin_amdgcn_alignbyte(v.y, v.x, sh);
+                const uint32_t e1 = __builtin_amdgcn_alignbyte(v.z, v.y, sh);
+                const uint32_t e2 = __builtin_amdgcn_alignbyte(v.w, v.z, sh);
+                X = (e0 & 0xFFu) | ((e0 >> 16) & 0xFF00u) | (e1 & 0xFF0000u) | ((e2 << 16) & 0xFF000000u);
+                b4 = (v.w >> (8 * sh)) & 0xFFu;
+            } else {
+                uint32_t qq = q;
+                X = 0;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    X |= static_cast<uint32_t>(row[3 * qq]) << (8 * m);
+                    qq = (qq + 1 == w) ? 0 : qq + 1;
+                }
+                b4 = row[3 * qq];
+            }
+            *reinterpret_cast<uint32_t *>(dst + 4 * u) = __builtin_amdgcn_alignbit(b4, X, t);
+            q += 4;
+            if (q >= w) q -= w;
+        }
+    }
+    __syncthreads();
+
+    // Phase 2: C[i][j0+k][c] = S[(i - d_v(c, j0+k)) mod h][c][k] ^ B.
+    uint8_t *__restrict__ outp = d.out + 3 * j0;
+    const uint8_t *__restrict__ Bp = d.B + 3 * j0;
+    if (aligned) {
+        constexpr uint32_t GPR = 3 * WT / 4;  // dwords per full strip row
+        constexpr uint32_t RP = NT / GPR;     // rows per pass
+        const uint32_t gpr = 3 * wt / 4;
+        const uint32_t g = threadIdx.x % GPR, i0 = threadIdx.x / GPR;
+        if (i0 < RP && g < gpr && i0 < h) {
+            uint32_t addr[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const uint32_t p = 4 * g + m, k = p / 3, c = p - 3 * k;
+                const uint32_t dv = mod16(D[3 * h + c * w + j0 + k], h, geo.inv_h);
+                const uint32_t r = (i0 >= dv) ? i0 - dv : i0 + h - dv;
+                addr[m] = r * RS + c * WT + k;
+            }
+            const uint32_t step = RP % h;
+            const uint32_t stepA = step * RS, wrapA = h * RS;
+            uint64_t off = static_cast<uint64_t>(i0) * row_bytes + 4 * g;
+            const uint64_t offstep = static_cast<uint64_t>(RP) * row_bytes;
+            for (uint32_t i = i0; i < h; i += RP) {
+                uint32_t v = static_cast<uint32_t>(S[addr[0]]) | (static_cast<uint32_t>(S[addr[1]]) << 8) |
+                             (static_cast<uint32_t>(S[addr[2]]) << 16) |
+                             (static_cast<uint32_t>(S[addr[3]]) << 24);
+                v ^= *reinterpret_cast<const uint32_t *>(Bp + off);
+                *reinterpret_cast<uint32_t *>(outp + off) = v;
+                off += offstep;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    addr[m] += stepA;
+                    if (addr[m] >= wrapA) addr[m] -= wrapA;
+                }
+            }
+        }
+    } else {
+        const uint32_t rowlen = 3 * wt;
+        const uint32_t items2 = h * rowlen;
+        for (uint32_t it = threadIdx.x; it < items2; it += NT) {
+            const uint32_t i = it / rowlen, p = it - i * rowlen;
+            const uint32_t k = p / 3, c = p - 3 * k;
+            const uint32_t dv = mod16(D[3 * h + c * w + j0 + k], h, geo.inv_h);
+            const uint32_t r = (i >= dv) ? i - dv : i + h - dv;
+            const uint64_t off = static_cast<uint64_t>(i) * row_bytes + p;
+            outp[off] = S[r * RS + c * WT + k] ^ Bp[off];
+        }
+    }
+}
+
+// ----------------------------------------------------------------------
+// Decryption
+// ----------------------------------------------------------------------
+// LDS row: channel c at c*CS + k for strip columns k = 0..wt (column wt is
+// pixel (j0 + wt) mod w, needed by the funnel of the last column).
+template <int WT>
+constexpr uint32_t dec_cs() { return WT + 4; }
+
+template <int WT, int NT>
+__global__ __launch_bounds__(NT) void confuse_xor_dec(const FrameDesc *__restrict__ desc, uint32_t first,
+                                                      uint32_t nframes, Geometry geo, uint32_t nstrips,
+                                                      int xcd_map, int aligned) {
+    extern __shared__ __align__(16) uint8_t S[];
+    constexpr uint32_t CS = dec_cs<WT>();
+    constexpr uint32_t RS = 3 * CS;
+    constexpr uint32_t KG = WT / 4;
+    constexpr uint32_t KPL = KG < 4 ? KG : 4;
+    constexpr uint32_t LPG = KG / KPL;
+
+    uint32_t fl, strip;
+    map_workgroup(blockIdx.x, nstrips, xcd_map, fl, strip);
+    if (fl >= nframes) return;
+    const FrameDesc d = desc[first + fl];
+    const uint32_t w = geo.w, h = geo.h, W8 = geo.W8, row_bytes = geo.row_bytes;
+    const uint32_t j0 = strip * WT;
+    const uint32_t wt = (w - j0 < static_cast<uint32_t>(WT)) ? w - j0 : WT;
+    const uint16_t *__restrict__ D = d.D;
+    const uint8_t *__restrict__ Cp = d.in + 3 * j0;
+    const uint8_t *__restrict__ Bp = d.B + 3 * j0;
+
+    // Phase 1: Y = C ^ B; undo Eq. 3: S[(i - d_v) mod h][c][k] = Y[i][j0+k][c].
+    if (aligned) {
+        constexpr uint32_t GPR = 3 * WT / 4;
+        constexpr uint32_t RP = NT / GPR;
+        const uint32_t gpr = 3 * wt / 4;
+        const uint32_t g = threadIdx.x % GPR, i0 = threadIdx.x / GPR;
+        if (i0 < RP && g < gpr && i0 < h) {
+            uint32_t addr[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const uint32_t p = 4 * g + m, k = p / 3, c = p - 3 * k;
+                const uint32_t dv = mod16(D[3 * h + c * w + j0 + k], h, geo.inv_h);
+                const uint32_t r = (i0 >= dv) ? i0 - dv : i0 + h - dv;
+                addr[m] = r * RS + c * CS + k;
+            }
+            const uint32_t step = RP % h;
+            const uint32_t stepA = step * RS, wrapA = h * RS;
+            uint64_t off = static_cast<uint64_t>(i0) * row_bytes + 4 * g;
+            const uint64_t offstep = static_cast<uint64_t>(RP) * row_bytes;
+            for (uint32_t i = i0; i < h; i += RP) {
+                const uint32_t y = *reinterpret_cast<const uint32_t *>(Cp + off) ^
+                                   *reinterpret_cast<const uint32_t *>(Bp + off);
+                S[addr[0]] = static_cast<uint8_t>(y);
+                S[addr[1]] = static_cast<uint8_t>(y >> 8);
+                S[addr[2]] = static_cast<uint8_t>(y >> 16);
+                S[addr[3]] = static_cast<uint8_t>(y >> 24);
+                off += offstep;
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    addr[m] += stepA;
+                    if (addr[m] >= wrapA) addr[m] -= wrapA;
+                }
+            }
+        }
+    } else {
+        const uint32_t rowlen = 3 * wt;
+        const uint32_t items = h * rowlen;
+        for (uint32_t it = threadIdx.x; it < items; it += NT) {
+            const uint32_t i = it / rowlen, p = it - i * rowlen;
+            const uint32_t k = p / 3, c = p - 3 * k;
+            const uint32_t dv = mod16(D[3 * h + c * w + j0 + k], h, geo.inv_h);
+            const uint32_t r = (i >= dv) ? i - dv : i + h - dv;
+            const uint64_t off = static_cast<uint64_t>(i) * row_bytes + p;
+            S[r * RS + c * CS + k] = Cp[off] ^ Bp[off];
+        }
+    }
+    // the extra column (j0 + wt) mod w, stored at k = wt
+    {
+        const uint32_t je = (j0 + wt == w) ? 0 : j0 + wt;
+        const uint8_t *Ce = d.in + 3 * je;
+        const uint8_t *Be = d.B + 3 * je;
+        for (uint32_t it = threadIdx.x; it < 3 * h; it += NT) {
+            const uint32_t i = it / 3, c = it - 3 * i;
+            const uint32_t dv = mod16(D[3 * h + c * w + je], h, geo.inv_h);
+            const uint32_t r = (i >= dv) ? i - dv : i + h - dv;
+            const uint64_t off = static_cast<uint64_t>(i) * row_bytes + c;
+            S[r * RS + c * CS + wt] = Ce[off] ^ Be[off];
+        }
+    }
+    __syncthreads();
+
+    // Phase 2: undo Eq. 2.  With a = (d_h mod 8w) >> 3 and t = d_h & 7,
+    // plaintext pixel q = (j0 + k - a) mod w of row r, channel c is the
+    // funnel shift of strip columns k and k+1 by t.
+    const uint32_t items2 = h * 3 * LPG;
+    for (uint32_t it = threadIdx.x; it < items2; it += NT) {
+        const uint32_t kl = it % LPG, rc = it / LPG;
+        const uint32_t r = rc / 3, c = rc - 3 * r;
+        const uint32_t dh = mod16(D[c * h + r], W8, geo.inv_W8);
+        const uint32_t a = dh >> 3, t = dh & 7;
+        uint32_t q = (j0 >= a) ? j0 - a : j0 + w - a;
+        uint32_t k = 4 * KPL * kl;
+        q += k;
+        if (q >= w) q -= w;
+        uint8_t *row = d.out + static_cast<uint64_t>(r) * row_bytes + c;
+        const uint8_t *src = S + r * RS + c * CS;
+#pragma unroll
+        for (uint32_t u = 0; u < KPL; ++u) {
+            if (k < wt) {
+                const uint32_t X = *reinterpret_cast<const uint32_t *>(src + k);
+                const uint32_t b4 = src[k + 4];
+                const uint32_t v = __builtin_amdgcn_alignbit(b4, X, t);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    if (k + m < wt) row[3 * q] = static_cast<uint8_t>(v >> (8 * m));
+                    q = (q + 1 == w) ? 0 : q + 1;
+                }
+            }
+            k += 4;
+        }
+    }
+}
+
+constexpr uint32_t kStrips[] = {4, 8, 16, 32, 64};
+constexpr uint32_t kThreads[] = {256, 512, 1024};
+
+template <int WT, int NT>
+hipError_t launch_one(int decrypt, const FrameDesc *d_desc, uint32_t first, uint32_t count, const Geometry &g,
+                      bool aligned, int xcd_map, hipStream_t s) {
+    const uint32_t nstrips = (g.w + WT - 1) / WT;
+    const uint64_t groups =
+        xcd_map ? 8ull * ((count + 7) / 8) * nstrips : static_cast<uint64_t>(count) * nstrips;
+    if (groups > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    const uint32_t lds = confuse_lds_bytes(decrypt, g.h, WT);
+    if (decrypt)
+        hipLaunchKernelGGL((confuse_xor_dec<WT, NT>), dim3(static_cast<uint32_t>(groups)), dim3(NT), lds, s,
+                           d_desc, first, count, g, nstrips, xcd_map, aligned ? 1 : 0);
+    else
+        hipLaunchKernelGGL((confuse_xor_enc<WT, NT>), dim3(static_cast<uint32_t>(groups)), dim3(NT), lds, s,
+                           d_desc, first, count, g, nstrips, xcd_map, aligned ? 1 : 0);
+    return hipGetLastError();
+}
+
+template <int WT>
+hipError_t launch_wt(int decrypt, const FrameDesc *d_desc, uint32_t first, uint32_t count, const Geometry &g,
+                     bool aligned, const ConfuseTuning &t, hipStream_t s) {
+    switch (t.threads) {
+    case 256: return launch_one<WT, 256>(decrypt, d_desc, first, count, g, aligned, t.xcd_map, s);
+    case 1024: return launch_one<WT, 1024>(decrypt, d_desc, first, count, g, aligned, t.xcd_map, s);
+    default: return launch_one<WT, 512>(decrypt, d_desc, first, count, g, aligned, t.xcd_map, s);
+    }
+}
+
+template <int WT, int NT>
+hipError_t set_lds_attr(uint32_t limit) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&confuse_xor_enc<WT, NT>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(limit));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&confuse_xor_dec<WT, NT>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(limit));
+}
+
+template <int WT>
+hipError_t set_lds_attr_wt(uint32_t limit) {
+    hipError_t e = set_lds_attr<WT, 256>(limit);
+    if (e == hipSuccess) e = set_lds_attr<WT, 512>(limit);
+    if (e == hipSuccess) e = set_lds_attr<WT, 1024>(limit);
+    return e;
+}
+
+}  // namespace
+
+uint32_t confuse_lds_bytes(int decrypt, uint32_t h, uint32_t strip) {
+    return decrypt ? h * 3 * (strip + 4) : h * 3 * strip;
+}
+
+uint32_t confuse_max_strip(int decrypt, uint32_t h, uint32_t lds_bytes) {
+    uint32_t best = 0;
+    for (uint32_t wt : kStrips)
+        if (static_cast<uint64_t>(confuse_lds_bytes(decrypt, h, wt)) <= lds_bytes) best = wt;
+    return best;
+}
+
+hipError_t confuse_configure(uint32_t lds_limit) {
+    hipError_t e = set_lds_attr_wt<4>(lds_limit);
+    if (e == hipSuccess) e = set_lds_attr_wt<8>(lds_limit);
+    if (e == hipSuccess) e = set_lds_attr_wt<16>(lds_limit);
+    if (e == hipSuccess) e = set_lds_attr_wt<32>(lds_limit);
+    if (e == hipSuccess) e = set_lds_attr_wt<64>(lds_limit);
+    return e;
+}
+
+hipError_t launch_confuse(int decrypt, const FrameDesc *d_desc, uint32_t first, uint32_t count, uint32_t w,
+                          uint32_t h, bool aligned, const ConfuseTuning &t, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    Geometry g;
+    g.w = w;
+    g.h = h;
+    g.W8 = 8 * w;
+    g.row_bytes = 3 * w;
+    g.inv_h = 1.0f / static_cast<float>(h);
+    g.inv_W8 = 1.0f / static_cast<float>(g.W8);
+    switch (t.strip) {
+    case 4: return launch_wt<4>(decrypt, d_desc, first, count, g, aligned, t, s);
+    case 8: return launch_wt<8>(decrypt, d_desc, first, count, g, aligned, t, s);
+    case 16: return launch_wt<16>(decrypt, d_desc, first, count, g, aligned, t, s);
+    case 32: return launch_wt<32>(decrypt, d_desc, first, count, g, aligned, t, s);
+    case 64: return launch_wt<64>(decrypt, d_desc, first, count, g, aligned, t, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace vc

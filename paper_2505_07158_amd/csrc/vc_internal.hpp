@@ -1,0 +1,61 @@
+// vc_internal.hpp -- types shared by the kernels and the C-ABI layer of
+// libvcipher (gfx950).  Not installed; the public interface is vcipher.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vc {
+
+// Per-frame work descriptor, packed on the host for every batch chunk and
+// read by all kernels (uniform per workgroup, so it lands in SGPRs).
+struct FrameDesc {
+    const uint8_t *in;   // plaintext (encrypt) or ciphertext (decrypt), h*w*3
+    uint8_t *out;        // output frame, h*w*3
+    uint8_t *hash;       // 32-byte frame hash H
+    double *IR;          // 2n x 4 LHCS_m iterates
+    uint16_t *D;         // 3h + 3w shift distances
+    uint8_t *B;          // 3wh keystream bytes
+    uint32_t w, h;
+    uint64_t L;          // 3wh
+};
+
+// One stream's frames inside a chunk, in sequence order: descriptor indices
+// order[first .. first+count).
+struct StreamRun {
+    uint32_t slot;       // chain-state slot
+    uint32_t first;
+    uint32_t count;
+    uint32_t pad;
+};
+
+enum KernelId { K_SHA = 0, K_CHAIN = 1, K_KEYGEN = 2, K_ENC = 3, K_DEC = 4, K_COUNT = 5 };
+
+struct ConfuseTuning {
+    uint32_t strip;      // pixels per strip (multiple of 4)
+    uint32_t threads;    // 256, 512 or 1024
+    int xcd_map;         // keep all strips of a frame on one XCD
+};
+
+// Device flag bits (int at d_flags[0]).
+enum { FLAG_NONFINITE = 1 };
+
+// Launchers (each in the translation unit of its kernel).
+hipError_t launch_sha256_subframes(const FrameDesc *d_desc, uint32_t count, uint32_t n,
+                                   hipStream_t s);
+hipError_t launch_lhcs_chain(const FrameDesc *d_desc, const StreamRun *d_runs,
+                             const uint32_t *d_order, uint32_t nruns, double *d_state,
+                             uint32_t n, double gamma, int *d_flags, hipStream_t s);
+hipError_t launch_lhcs_keygen(const FrameDesc *d_desc, uint32_t count, uint32_t n,
+                              double gamma, int *d_flags, hipStream_t s);
+// Frames [first, first + count) of d_desc all have shape (w, h).
+hipError_t launch_confuse(int decrypt, const FrameDesc *d_desc, uint32_t first, uint32_t count,
+                          uint32_t w, uint32_t h, bool aligned, const ConfuseTuning &t,
+                          hipStream_t s);
+// Largest strip width the LDS holds for height h (0 if none), given the
+// per-workgroup LDS budget.
+uint32_t confuse_max_strip(int decrypt, uint32_t h, uint32_t lds_bytes);
+uint32_t confuse_lds_bytes(int decrypt, uint32_t h, uint32_t strip);
+hipError_t confuse_configure(uint32_t lds_limit);
+
+}  // namespace vc

@@ -1,0 +1,384 @@
+"""ctypes binding of libvcipher (include/vcipher.h).
+
+Argument marshalling only: every step of the cipher runs in the library's HIP
+kernels.  Functions carry the C names; torch tensors supply device memory and
+the current HIP stream.  There is no CPU fallback: if the shared library is
+missing the import of this module fails.
+
+Frames are ``torch.uint8`` CUDA tensors of shape ``(h, w, 3)`` (or a batch
+``(T, h, w, 3)``), contiguous.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Iterable, List, Optional, Sequence, Tuple, Union
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvcipher.so")
+
+VC_OK, VC_EINVAL, VC_ENOMEM, VC_EDEVICE, VC_EORDER, VC_ENONFINITE, VC_EBUSY = 0, -1, -2, -3, -4, -5, -6
+KERNELS = ("sha256_subframes", "lhcs_chain", "lhcs_keygen", "confuse_xor_enc", "confuse_xor_dec")
+
+
+class VcKey(C.Structure):
+    _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double), ("w0", C.c_double),
+                ("gamma", C.c_double), ("n", C.c_uint32)]
+
+
+class VcShape(C.Structure):
+    _fields_ = [("w", C.c_uint32), ("h", C.c_uint32), ("c", C.c_uint32),
+                ("stream", C.c_uint32), ("seq", C.c_uint64)]
+
+
+class VcError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: {strerror(status)} ({status})")
+        self.status = status
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2505_07158_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    vp, u8p = C.c_void_p, C.c_void_p
+    L.vc_protocol_version.restype = C.c_uint32
+    L.vc_protocol_version.argtypes = []
+    L.vc_strerror.restype = C.c_char_p
+    L.vc_strerror.argtypes = [C.c_int]
+    L.vc_kernel_name.restype = C.c_char_p
+    L.vc_kernel_name.argtypes = [C.c_int]
+    L.vc_key_from_bytes.argtypes = [C.c_char_p, C.c_double, C.c_uint32, C.POINTER(VcKey)]
+    L.cipher_init.argtypes = [C.POINTER(VcKey), C.c_uint32, C.c_size_t, C.POINTER(vp)]
+    L.cipher_destroy.argtypes = [vp]
+    L.cipher_destroy.restype = None
+    L.encrypt_frames.argtypes = [vp, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape), u8p, C.POINTER(vp), vp]
+    L.decrypt_frames.argtypes = [vp, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape), u8p, C.POINTER(vp), vp]
+    L.vc_hash_frames.argtypes = [vp, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape), u8p, vp]
+    L.cipher_stream_reset.argtypes = [vp, C.c_uint32]
+    L.cipher_stream_get_state.argtypes = [vp, C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
+    L.cipher_stream_set_state.argtypes = [vp, C.c_uint32, C.POINTER(C.c_double), C.c_uint64]
+    L.cipher_status.argtypes = [vp, vp]
+    L.vc_profile_enable.argtypes = [vp, C.c_int]
+    L.vc_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
+    L.vc_profile_reset.argtypes = [vp]
+    L.vc_set_tuning.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_int]
+    L.vc_debug_confuse.argtypes = [vp, C.c_int, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape),
+                                   C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
+    L.vc_debug_keysched.argtypes = [vp, C.c_size_t, C.POINTER(VcShape), u8p, C.POINTER(vp),
+                                    C.POINTER(vp), C.POINTER(vp), vp]
+    for name in ("cipher_init", "encrypt_frames", "decrypt_frames", "vc_hash_frames", "cipher_stream_reset",
+                 "cipher_stream_get_state", "cipher_stream_set_state", "cipher_status",
+                 "vc_profile_enable", "vc_profile_read", "vc_profile_reset", "vc_set_tuning",
+                 "vc_debug_confuse", "vc_debug_keysched", "vc_key_from_bytes"):
+        getattr(L, name).restype = C.c_int
+    return L
+
+
+lib = _load()
+
+
+def strerror(status: int) -> str:
+    return lib.vc_strerror(status).decode()
+
+
+def vc_protocol_version() -> int:
+    return int(lib.vc_protocol_version())
+
+
+def vc_kernel_name(k: int) -> str:
+    return lib.vc_kernel_name(k).decode()
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != VC_OK:
+        raise VcError(rc, what)
+
+
+def vc_key_from_bytes(key32: bytes, gamma: float, n: int) -> VcKey:
+    key = VcKey()
+    _check(lib.vc_key_from_bytes(bytes(key32), gamma, n, C.byref(key)), "vc_key_from_bytes")
+    return key
+
+
+# --------------------------------------------------------------------------
+# marshalling helpers
+# --------------------------------------------------------------------------
+
+FrameArg = Union[torch.Tensor, Sequence[torch.Tensor]]
+
+
+def _frames(x: FrameArg) -> List[torch.Tensor]:
+    if isinstance(x, torch.Tensor):
+        if x.dim() == 3:
+            return [x]
+        if x.dim() == 4:
+            return [x[i] for i in range(x.shape[0])]
+        raise ValueError("frames must be (h, w, 3) or (T, h, w, 3)")
+    return list(x)
+
+
+def _check_frame(t: torch.Tensor) -> None:
+    if t.dtype != torch.uint8 or not t.is_cuda or t.dim() != 3 or t.shape[2] != 3:
+        raise ValueError("each frame must be a CUDA uint8 tensor of shape (h, w, 3)")
+    if not t.is_contiguous():
+        raise ValueError("frames must be contiguous")
+
+
+def _ptrs(ts: Sequence[torch.Tensor]):
+    arr = (C.c_void_p * max(len(ts), 1))()
+    for i, t in enumerate(ts):
+        arr[i] = t.data_ptr()
+    return arr
+
+
+def _shapes(ts: Sequence[torch.Tensor], streams: Sequence[int], seqs: Sequence[int]):
+    arr = (VcShape * max(len(ts), 1))()
+    for i, t in enumerate(ts):
+        arr[i] = VcShape(int(t.shape[1]), int(t.shape[0]), int(t.shape[2]), int(streams[i]), int(seqs[i]))
+    return arr
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream]) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+# --------------------------------------------------------------------------
+# the C functions, one to one
+# --------------------------------------------------------------------------
+
+def cipher_init(key: VcKey, max_streams: int = 1, scratch_bytes: int = 0) -> int:
+    h = C.c_void_p()
+    _check(lib.cipher_init(C.byref(key), max_streams, scratch_bytes, C.byref(h)), "cipher_init")
+    return int(h.value)
+
+
+def cipher_destroy(ctx: int) -> None:
+    lib.cipher_destroy(C.c_void_p(ctx))
+
+
+def encrypt_frames(ctx: int, frames: Sequence[torch.Tensor], streams: Sequence[int], seqs: Sequence[int],
+                   hashes: torch.Tensor, out: Sequence[torch.Tensor],
+                   stream: Optional[torch.cuda.Stream] = None) -> None:
+    for t in list(frames) + list(out):
+        _check_frame(t)
+    if hashes.dtype != torch.uint8 or not hashes.is_cuda or hashes.numel() < 32 * len(frames):
+        raise ValueError("hashes must be a CUDA uint8 tensor of count*32 bytes")
+    rc = lib.encrypt_frames(C.c_void_p(ctx), len(frames), _ptrs(frames), _shapes(frames, streams, seqs),
+                            C.c_void_p(hashes.data_ptr()), _ptrs(out), C.c_void_p(_stream_handle(stream)))
+    _check(rc, "encrypt_frames")
+
+
+def decrypt_frames(ctx: int, frames: Sequence[torch.Tensor], streams: Sequence[int], seqs: Sequence[int],
+                   hashes: torch.Tensor, out: Sequence[torch.Tensor],
+                   stream: Optional[torch.cuda.Stream] = None) -> None:
+    for t in list(frames) + list(out):
+        _check_frame(t)
+    if hashes.dtype != torch.uint8 or not hashes.is_cuda or hashes.numel() < 32 * len(frames):
+        raise ValueError("hashes must be a CUDA uint8 tensor of count*32 bytes")
+    rc = lib.decrypt_frames(C.c_void_p(ctx), len(frames), _ptrs(frames), _shapes(frames, streams, seqs),
+                            C.c_void_p(hashes.data_ptr()), _ptrs(out), C.c_void_p(_stream_handle(stream)))
+    _check(rc, "decrypt_frames")
+
+
+def vc_hash_frames(ctx: int, frames: Sequence[torch.Tensor], hashes: torch.Tensor,
+                   stream: Optional[torch.cuda.Stream] = None) -> None:
+    for t in frames:
+        _check_frame(t)
+    zeros = [0] * len(frames)
+    rc = lib.vc_hash_frames(C.c_void_p(ctx), len(frames), _ptrs(frames), _shapes(frames, zeros, zeros),
+                            C.c_void_p(hashes.data_ptr()), C.c_void_p(_stream_handle(stream)))
+    _check(rc, "vc_hash_frames")
+
+
+def vc_debug_confuse(ctx: int, decrypt: bool, frames: Sequence[torch.Tensor], D: Sequence[torch.Tensor],
+                     B: Sequence[torch.Tensor], out: Sequence[torch.Tensor],
+                     stream: Optional[torch.cuda.Stream] = None) -> None:
+    for t in list(frames) + list(out):
+        _check_frame(t)
+    zeros = [0] * len(frames)
+    rc = lib.vc_debug_confuse(C.c_void_p(ctx), 1 if decrypt else 0, len(frames), _ptrs(frames),
+                              _shapes(frames, zeros, zeros), _ptrs(D), _ptrs(B), _ptrs(out),
+                              C.c_void_p(_stream_handle(stream)))
+    _check(rc, "vc_debug_confuse")
+
+
+def vc_debug_keysched(ctx: int, shapes_hw: Sequence[Tuple[int, int]], streams: Sequence[int],
+                      seqs: Sequence[int], hashes: torch.Tensor, IR: Sequence[torch.Tensor],
+                      D: Sequence[torch.Tensor], B: Sequence[torch.Tensor],
+                      stream: Optional[torch.cuda.Stream] = None) -> None:
+    arr = (VcShape * max(len(shapes_hw), 1))()
+    for i, (h, w) in enumerate(shapes_hw):
+        arr[i] = VcShape(w, h, 3, int(streams[i]), int(seqs[i]))
+    rc = lib.vc_debug_keysched(C.c_void_p(ctx), len(shapes_hw), arr, C.c_void_p(hashes.data_ptr()),
+                               _ptrs(IR), _ptrs(D), _ptrs(B), C.c_void_p(_stream_handle(stream)))
+    _check(rc, "vc_debug_keysched")
+
+
+def cipher_stream_reset(ctx: int, stream: int) -> None:
+    _check(lib.cipher_stream_reset(C.c_void_p(ctx), stream), "cipher_stream_reset")
+
+
+def cipher_stream_get_state(ctx: int, stream: int) -> Tuple[List[float], int]:
+    st = (C.c_double * 4)()
+    nxt = C.c_uint64()
+    _check(lib.cipher_stream_get_state(C.c_void_p(ctx), stream, st, C.byref(nxt)), "cipher_stream_get_state")
+    return list(st), int(nxt.value)
+
+
+def cipher_stream_set_state(ctx: int, stream: int, st: Sequence[float], next_seq: int) -> None:
+    arr = (C.c_double * 4)(*[float(v) for v in st])
+    _check(lib.cipher_stream_set_state(C.c_void_p(ctx), stream, arr, next_seq), "cipher_stream_set_state")
+
+
+def cipher_status(ctx: int, stream: Optional[torch.cuda.Stream] = None) -> int:
+    return int(lib.cipher_status(C.c_void_p(ctx), C.c_void_p(_stream_handle(stream))))
+
+
+def vc_profile_enable(ctx: int, enable: bool) -> None:
+    _check(lib.vc_profile_enable(C.c_void_p(ctx), 1 if enable else 0), "vc_profile_enable")
+
+
+def vc_profile_read(ctx: int, kernel_id: int) -> Tuple[float, int]:
+    ms = C.c_double()
+    n = C.c_uint64()
+    _check(lib.vc_profile_read(C.c_void_p(ctx), kernel_id, C.byref(ms), C.byref(n)), "vc_profile_read")
+    return float(ms.value), int(n.value)
+
+
+def vc_profile_reset(ctx: int) -> None:
+    _check(lib.vc_profile_reset(C.c_void_p(ctx)), "vc_profile_reset")
+
+
+def vc_set_tuning(ctx: int, strip_width: int = 0, threads: int = 0, xcd_map: bool = True) -> None:
+    _check(lib.vc_set_tuning(C.c_void_p(ctx), strip_width, threads, 1 if xcd_map else 0), "vc_set_tuning")
+
+
+# --------------------------------------------------------------------------
+# convenience wrapper
+# --------------------------------------------------------------------------
+
+class Cipher:
+    """One cipher context (key, chain states, scratch) on the current device.
+
+    Tracks each stream's next sequence number on the host so callers can
+    pass frames in order without numbering them."""
+
+    def __init__(self, key: VcKey, max_streams: int = 1, scratch_bytes: int = 0):
+        self.key = key
+        self.n = int(key.n)
+        self.max_streams = max_streams
+        self.ctx = cipher_init(key, max_streams, scratch_bytes)
+        self._next = [0] * max_streams
+
+    @classmethod
+    def from_bytes(cls, key32: bytes, gamma: float, n: int, **kw) -> "Cipher":
+        return cls(vc_key_from_bytes(key32, gamma, n), **kw)
+
+    def close(self) -> None:
+        if self.ctx:
+            cipher_destroy(self.ctx)
+            self.ctx = 0
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _seqs(self, streams: Sequence[int]) -> List[int]:
+        nxt = list(self._next)
+        out = []
+        for s in streams:
+            out.append(nxt[s])
+            nxt[s] += 1
+        return out
+
+    def _advance(self, streams: Sequence[int]) -> None:
+        for s in streams:
+            self._next[s] += 1
+
+    def encrypt(self, frames: FrameArg, streams: Optional[Sequence[int]] = None,
+                out: Optional[FrameArg] = None, hashes: Optional[torch.Tensor] = None,
+                stream: Optional[torch.cuda.Stream] = None):
+        """Encrypt frames (in sequence order per stream). Returns (out, hashes)."""
+        fr = _frames(frames)
+        streams = list(streams) if streams is not None else [0] * len(fr)
+        if out is None:
+            if isinstance(frames, torch.Tensor):
+                out_t = torch.empty_like(frames)
+                out = out_t
+            else:
+                out = [torch.empty_like(t) for t in fr]
+        outs = _frames(out)
+        if hashes is None:
+            hashes = torch.empty((len(fr), 32), dtype=torch.uint8, device=fr[0].device)
+        encrypt_frames(self.ctx, fr, streams, self._seqs(streams), hashes, outs, stream)
+        self._advance(streams)
+        return out, hashes
+
+    def decrypt(self, frames: FrameArg, hashes: torch.Tensor, streams: Optional[Sequence[int]] = None,
+                out: Optional[FrameArg] = None, stream: Optional[torch.cuda.Stream] = None):
+        fr = _frames(frames)
+        streams = list(streams) if streams is not None else [0] * len(fr)
+        if out is None:
+            out = torch.empty_like(frames) if isinstance(frames, torch.Tensor) else [torch.empty_like(t) for t in fr]
+        outs = _frames(out)
+        decrypt_frames(self.ctx, fr, streams, self._seqs(streams), hashes, outs, stream)
+        self._advance(streams)
+        return out
+
+    def hash(self, frames: FrameArg, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+        fr = _frames(frames)
+        hashes = torch.empty((len(fr), 32), dtype=torch.uint8, device=fr[0].device)
+        vc_hash_frames(self.ctx, fr, hashes, stream)
+        return hashes
+
+    def keysched(self, shapes_hw: Sequence[Tuple[int, int]], hashes: torch.Tensor,
+                 streams: Optional[Sequence[int]] = None, stream: Optional[torch.cuda.Stream] = None):
+        """Key schedule only (testing): returns lists IR (2n x 4 float64), D (uint16), B (h, w, 3)."""
+        streams = list(streams) if streams is not None else [0] * len(shapes_hw)
+        dev = hashes.device
+        IR = [torch.empty((2 * self.n, 4), dtype=torch.float64, device=dev) for _ in shapes_hw]
+        D = [torch.empty(3 * h + 3 * w, dtype=torch.int16, device=dev) for h, w in shapes_hw]
+        B = [torch.empty((h, w, 3), dtype=torch.uint8, device=dev) for h, w in shapes_hw]
+        vc_debug_keysched(self.ctx, shapes_hw, streams, self._seqs(streams), hashes, IR, D, B, stream)
+        self._advance(streams)
+        return IR, D, B
+
+    def confuse(self, frames: FrameArg, D: Sequence[torch.Tensor], B: Sequence[torch.Tensor],
+                decrypt: bool = False, stream: Optional[torch.cuda.Stream] = None):
+        """Confusion + XOR (or inverse) with given D/B (testing)."""
+        fr = _frames(frames)
+        outs = [torch.empty_like(t) for t in fr]
+        vc_debug_confuse(self.ctx, decrypt, fr, D, B, outs, stream)
+        return outs
+
+    def reset(self, s: int = 0) -> None:
+        cipher_stream_reset(self.ctx, s)
+        self._next[s] = 0
+
+    def get_state(self, s: int = 0):
+        return cipher_stream_get_state(self.ctx, s)
+
+    def set_state(self, s: int, st: Sequence[float], next_seq: int) -> None:
+        cipher_stream_set_state(self.ctx, s, st, next_seq)
+        self._next[s] = next_seq
+
+    def status(self, stream: Optional[torch.cuda.Stream] = None) -> int:
+        return cipher_status(self.ctx, stream)
+
+    def profile(self, enable: bool = True) -> None:
+        vc_profile_enable(self.ctx, enable)
+
+    def profile_read(self):
+        return {KERNELS[k]: vc_profile_read(self.ctx, k) for k in range(len(KERNELS))}
+
+    def profile_reset(self) -> None:
+        vc_profile_reset(self.ctx)
+
+    def tune(self, strip_width: int = 0, threads: int = 0, xcd_map: bool = True) -> None:
+        vc_set_tuning(self.ctx, strip_width, threads, xcd_map)

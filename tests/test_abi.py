@@ -1,0 +1,84 @@
+"""The C-ABI library loads and exports every function include/vcipher.h
+declares; host-only logic (key bytes, validation before any device call)
+behaves as documented.  No GPU needed."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "vcipher.h")
+LIB = os.path.join(ROOT, "paper_2505_07158_amd", "libvcipher.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    names = re.findall(r"\b([A-Za-z_]\w*)\s*\([^;{}()]*(?:\([^)]*\)[^;{}()]*)*\)\s*;", text)
+    return sorted(set(n for n in names if n not in ("if", "while", "sizeof")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        import paper_2505_07158_amd.build as b
+        b.build()
+    return C.CDLL(LIB)
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for required in ("cipher_init", "encrypt_frames", "decrypt_frames", "cipher_destroy"):
+        assert required in names
+    assert len(names) >= 15
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_host_only_functions(lib):
+    lib.vc_protocol_version.restype = C.c_uint32
+    assert lib.vc_protocol_version() == 1
+    lib.vc_strerror.restype = C.c_char_p
+    for code in range(-7, 1):
+        assert lib.vc_strerror(code)
+    lib.vc_kernel_name.restype = C.c_char_p
+    assert [lib.vc_kernel_name(k).decode() for k in range(5)] == [
+        "sha256_subframes", "lhcs_chain", "lhcs_keygen", "confuse_xor_enc", "confuse_xor_dec"]
+
+
+def test_key_from_bytes_agrees_with_oracle():
+    from paper_2505_07158_amd import vcipher as V
+    rng = np.random.default_rng(3)
+    for _ in range(50):
+        kb = rng.bytes(32)
+        k = V.vc_key_from_bytes(kb, -1.0, 32)
+        np.testing.assert_array_equal([k.x0, k.y0, k.z0, k.w0], oracle.key_from_bytes(kb))
+        assert k.gamma == -1.0 and k.n == 32
+
+
+@pytest.mark.parametrize("gamma,n", [(-1.6, 32), (-0.05, 32), (-1.0, 0), (-1.0, 1025), (float("nan"), 4)])
+def test_invalid_keys_rejected_before_device_use(gamma, n):
+    from paper_2505_07158_amd import vcipher as V
+    with pytest.raises(V.VcError) as e:
+        V.vc_key_from_bytes(bytes(32), gamma, n)
+    assert e.value.status == V.VC_EINVAL
+    key = V.VcKey(1.0, 2.0, 3.0, 4.0, gamma, n)
+    with pytest.raises(V.VcError) as e:
+        V.cipher_init(key, 1, 0)
+    assert e.value.status == V.VC_EINVAL
+
+
+def test_nonfinite_key_and_zero_streams_rejected():
+    from paper_2505_07158_amd import vcipher as V
+    for key, streams in ((V.VcKey(float("inf"), 0, 0, 0, -1.0, 4), 1), (V.VcKey(1, 2, 3, 4, -1.0, 4), 0)):
+        with pytest.raises(V.VcError) as e:
+            V.cipher_init(key, streams, 0)
+        assert e.value.status == V.VC_EINVAL

@@ -1,0 +1,205 @@
+"""End-to-end GPU parity of encrypt_frames / decrypt_frames against the
+oracle on the small workloads (one 64x64 frame for several worker counts;
+a 24-frame 640x480 video), the differential test of Sec. IV-B on the GPU
+path, multi-stream batches (each stream's bytes equal the stream run alone),
+chunked scratch, chain-state export/import and the documented errors."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_util import require_gpu, to_dev, to_np
+from metrics import npcr_critical, npcr_mean_sigma, npcr_uaci, uaci_interval, uaci_mean_sigma
+from workload.synth import SynthVideo, config1_frame, config2_video, key_bytes, random_frame
+
+pytestmark = pytest.mark.gpu
+
+
+def V():
+    from paper_2505_07158_amd import vcipher
+    return vcipher
+
+
+def oracle_stream(kb, gamma, n, frames):
+    return oracle.encrypt_stream(oracle.key_from_bytes(kb), gamma, n, frames)
+
+
+@pytest.mark.parametrize("n", [1, 6, 32, 64, 256])
+def test_config1_parity(n):
+    dev = require_gpu()
+    kb = key_bytes(0)
+    P = config1_frame()
+    c = V().Cipher.from_bytes(kb, -1.0, n)
+    C, H = c.encrypt(to_dev(P, dev)[None])
+    Cs, Hs, _ = oracle_stream(kb, -1.0, n, [P])
+    assert to_np(H)[0].tobytes() == Hs[0]
+    assert np.array_equal(to_np(C)[0], Cs[0])
+    d = V().Cipher.from_bytes(kb, -1.0, n)
+    Q = d.decrypt(C, H)
+    assert np.array_equal(to_np(Q)[0], P)
+    assert c.status() == 0 and d.status() == 0
+    c.close(); d.close()
+
+
+def test_config2_video_parity_and_roundtrip():
+    dev = require_gpu()
+    kb = key_bytes(0)
+    video = config2_video()
+    frames = video.frames(24)
+    c = V().Cipher.from_bytes(kb, -1.0, 32)
+    C, H = c.encrypt(to_dev(frames, dev))
+    Cs, Hs, end = oracle_stream(kb, -1.0, 32, list(frames))
+    Cn, Hn = to_np(C), to_np(H)
+    for t in range(24):
+        assert Hn[t].tobytes() == Hs[t], t
+        assert np.array_equal(Cn[t], Cs[t]), t
+    st, _ = c.get_state(0)
+    assert np.array_equal(np.array(st).view(np.uint64), end.view(np.uint64))
+    d = V().Cipher.from_bytes(kb, -1.0, 32)
+    Q = d.decrypt(C, H)
+    assert np.array_equal(to_np(Q), frames)
+    c.close(); d.close()
+
+
+def test_config2_differential_npcr_uaci():
+    """Sec. IV-B on the GPU path: frames 0-7 of the 640x480 video each get
+    one random pixel-channel increment; per channel the NPCR / UACI against
+    the unmodified encryption stay within five standard deviations of the
+    ideal-cipher means, and their averages pass the alpha = 0.05 tests."""
+    dev = require_gpu()
+    kb = key_bytes(0)
+    frames = config2_video().frames(8)
+    rng = np.random.default_rng(2)
+    h, w = 480, 640
+    M = h * w
+    mu_n, s_n = npcr_mean_sigma(M)
+    mu_u, s_u = uaci_mean_sigma(M)
+    npcrs, uacis = [], []
+    for t in range(8):
+        g = frames[t].copy()
+        i, j, ch = rng.integers(0, h), rng.integers(0, w), rng.integers(0, 3)
+        g[i, j, ch] = (int(g[i, j, ch]) + int(rng.integers(1, 256))) % 256
+        a = V().Cipher.from_bytes(kb, -1.0, 32)
+        b = V().Cipher.from_bytes(kb, -1.0, 32)
+        Ca, _ = a.encrypt(to_dev(frames[t], dev)[None])
+        Cb, _ = b.encrypt(to_dev(g, dev)[None])
+        npcr, uaci = npcr_uaci(to_np(Ca)[0], to_np(Cb)[0])
+        assert np.all(np.abs(npcr - mu_n) < 5 * s_n), npcr
+        assert np.all(np.abs(uaci - mu_u) < 5 * s_u), uaci
+        npcrs.append(npcr); uacis.append(uaci)
+        a.close(); b.close()
+    lo, hi = uaci_interval(M)
+    assert np.mean(npcrs) > npcr_critical(M)
+    assert lo < np.mean(uacis) < hi
+
+
+def test_modified_frame_changes_later_frames():
+    dev = require_gpu()
+    kb = key_bytes(1)
+    frames = SynthVideo(160, 120, seed=9).frames(3)
+    g = frames.copy()
+    g[0, 5, 5, 0] ^= 1
+    a = V().Cipher.from_bytes(kb, -1.0, 6)
+    b = V().Cipher.from_bytes(kb, -1.0, 6)
+    Ca, Ha = a.encrypt(to_dev(frames, dev))
+    Cb, Hb = b.encrypt(to_dev(g, dev))
+    Ha, Hb = to_np(Ha), to_np(Hb)
+    assert Ha[0].tobytes() != Hb[0].tobytes()
+    assert Ha[1].tobytes() == Hb[1].tobytes() and Ha[2].tobytes() == Hb[2].tobytes()
+    for t in range(3):
+        npcr, _ = npcr_uaci(to_np(Ca)[t], to_np(Cb)[t])
+        assert np.all(npcr > 99.0), (t, npcr)
+
+
+def test_multistream_mixed_batch_equals_streams_alone():
+    dev = require_gpu()
+    kb = key_bytes(3)
+    shapes = {0: (48, 64), 1: (30, 42), 2: (48, 64), 3: (17, 23)}
+    vids = {s: SynthVideo(w, h, seed=50 + s).frames(4) for s, (h, w) in shapes.items()}
+    # interleaved order: frame t of every stream, streams rotating
+    order = [(s, t) for t in range(4) for s in (2, 0, 3, 1)]
+    mixed = V().Cipher.from_bytes(kb, -1.0, 6, max_streams=4)
+    ins = [to_dev(vids[s][t], dev) for s, t in order]
+    outs, H = mixed.encrypt(ins, streams=[s for s, _ in order])
+    outs = [to_np(o) for o in outs]
+    Hn = to_np(H)
+    for s in shapes:
+        alone = V().Cipher.from_bytes(kb, -1.0, 6)
+        Ca, Hal = alone.encrypt(to_dev(vids[s], dev))
+        Ca, Hal = to_np(Ca), to_np(Hal)
+        Cs, Hs, _ = oracle_stream(kb, -1.0, 6, list(vids[s]))
+        for t in range(4):
+            k = order.index((s, t))
+            assert np.array_equal(outs[k], Ca[t]) and np.array_equal(outs[k], Cs[t]), (s, t)
+            assert Hn[k].tobytes() == Hal[t].tobytes() == Hs[t]
+        alone.close()
+    # and decrypt the mixed batch in the same order
+    dec = V().Cipher.from_bytes(kb, -1.0, 6, max_streams=4)
+    Cin = [to_dev(o, dev) for o in outs]
+    P = dec.decrypt(Cin, H, streams=[s for s, _ in order])
+    for (s, t), p in zip(order, P):
+        assert np.array_equal(to_np(p), vids[s][t])
+    mixed.close(); dec.close()
+
+
+def test_small_scratch_processes_in_chunks():
+    dev = require_gpu()
+    kb = key_bytes(4)
+    frames = SynthVideo(128, 96, seed=4).frames(7)
+    small = V().Cipher.from_bytes(kb, -1.0, 32, scratch_bytes=2 * 128 * 96 * 3 + 65536)
+    big = V().Cipher.from_bytes(kb, -1.0, 32)
+    C1, H1 = small.encrypt(to_dev(frames, dev))
+    C2, H2 = big.encrypt(to_dev(frames, dev))
+    assert torch.equal(C1, C2) and torch.equal(H1, H2)
+    small.close(); big.close()
+
+
+def test_state_export_import_resumes_stream():
+    dev = require_gpu()
+    kb = key_bytes(5)
+    frames = SynthVideo(64, 48, seed=5).frames(4)
+    a = V().Cipher.from_bytes(kb, -1.0, 8)
+    Ca, Ha = a.encrypt(to_dev(frames, dev))
+    b = V().Cipher.from_bytes(kb, -1.0, 8)
+    b.encrypt(to_dev(frames[:2], dev))
+    st, nxt = b.get_state(0)
+    assert nxt == 2
+    c = V().Cipher.from_bytes(kb, -1.0, 8)
+    c.set_state(0, st, 2)
+    Cc, Hc = c.encrypt(to_dev(frames[2:], dev))
+    assert torch.equal(Cc, Ca[2:]) and torch.equal(Hc, Ha[2:])
+    c.reset(0)
+    Cr, _ = c.encrypt(to_dev(frames[:1], dev))
+    assert torch.equal(Cr, Ca[:1])
+    a.close(); b.close(); c.close()
+
+
+def test_documented_errors():
+    dev = require_gpu()
+    Vm = V()
+    c = Vm.Cipher.from_bytes(key_bytes(6), -1.0, 8, max_streams=2)
+    f = to_dev(random_frame(16, 16, 1), dev)
+    out = torch.empty_like(f)
+    H = torch.empty((1, 32), dtype=torch.uint8, device=dev)
+    # out of sequence
+    with pytest.raises(Vm.VcError) as e:
+        Vm.encrypt_frames(c.ctx, [f], [0], [1], H, [out])
+    assert e.value.status == Vm.VC_EORDER
+    # in-place encryption (the gather cannot run in place)
+    with pytest.raises(Vm.VcError) as e:
+        Vm.encrypt_frames(c.ctx, [f], [0], [0], H, [f])
+    assert e.value.status == Vm.VC_EINVAL
+    # stream id out of range
+    with pytest.raises(Vm.VcError) as e:
+        Vm.encrypt_frames(c.ctx, [f], [2], [0], H, [out])
+    assert e.value.status == Vm.VC_EINVAL
+    # n larger than the frame
+    tiny = Vm.Cipher.from_bytes(key_bytes(6), -1.0, 8)
+    t = torch.zeros((1, 2, 3), dtype=torch.uint8, device=dev)
+    with pytest.raises(Vm.VcError) as e:
+        Vm.encrypt_frames(tiny.ctx, [t], [0], [0], H, [torch.empty_like(t)])
+    assert e.value.status == Vm.VC_EINVAL
+    # failed calls enqueue nothing: the stream still starts at seq 0
+    Vm.encrypt_frames(c.ctx, [f], [0], [0], H, [out])
+    assert c.status() == 0
+    c.close(); tiny.close()
