@@ -7,6 +7,15 @@
 
 namespace vc {
 
+// Pointers read out of descriptors are generic (flat) to the compiler;
+// casting them to the global address space turns flat loads and stores
+// (which also count against the LDS wait counter) into global ones.
+#define VC_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ VC_GLOBAL T *gmem(T *p) {
+    return (VC_GLOBAL T *)p;
+}
+
 // Per-frame work descriptor, packed on the host for every batch chunk and
 // read by all kernels (uniform per workgroup, so it lands in SGPRs).
 struct FrameDesc {

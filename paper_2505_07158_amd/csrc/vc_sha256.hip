@@ -118,7 +118,7 @@ __device__ __forceinline__ void sha_compress(uint32_t (&H)[8], uint32_t (&W)[16]
 __device__ __forceinline__ uint32_t bswap32(uint32_t x) { return __builtin_bswap32(x); }
 
 // Big-endian word m of a 64-byte block read byte by byte (bounded paths).
-__device__ __forceinline__ uint32_t load_be_bytes(const uint8_t *p) {
+__device__ __forceinline__ uint32_t load_be_bytes(const VC_GLOBAL uint8_t *p) {
     return (uint32_t(p[0]) << 24) | (uint32_t(p[1]) << 16) | (uint32_t(p[2]) << 8) | uint32_t(p[3]);
 }
 
@@ -127,17 +127,17 @@ __device__ __forceinline__ uint32_t load_be_bytes(const uint8_t *p) {
 typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
 
 // 17 consecutive dwords from a dword-aligned address.
-__device__ __forceinline__ void load_window(const uint32_t *p, uint32_t (&w)[17]) {
+__device__ __forceinline__ void load_window(const VC_GLOBAL uint32_t *p, uint32_t (&w)[17]) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const u32x4_a4 v = *reinterpret_cast<const u32x4_a4 *>(p + 4 * q);
+        const u32x4_a4 v = *reinterpret_cast<const VC_GLOBAL u32x4_a4 *>(p + 4 * q);
         w[4 * q] = v.x; w[4 * q + 1] = v.y; w[4 * q + 2] = v.z; w[4 * q + 3] = v.w;
     }
     w[16] = p[16];
 }
 
 // SHA-256 of bytes [a, b) of a frame of L bytes at `frame`.
-__device__ void sha256_range(const uint8_t *frame, uint64_t a, uint64_t b, uint64_t L,
+__device__ void sha256_range(const VC_GLOBAL uint8_t *frame, uint64_t a, uint64_t b, uint64_t L,
                              uint32_t (&H)[8]) {
 #pragma unroll
     for (int k = 0; k < 8; ++k) H[k] = kSha.H0[k];
@@ -156,7 +156,7 @@ __device__ void sha256_range(const uint8_t *frame, uint64_t a, uint64_t b, uint6
         nfast = (end - base - 68) / 64 + 1;
         if (nfast > nfull) nfast = nfull;
     }
-    const uint32_t *wp = reinterpret_cast<const uint32_t *>(base);
+    const VC_GLOBAL uint32_t *wp = reinterpret_cast<const VC_GLOBAL uint32_t *>(base);
     uint32_t W[16];
     if (nfast > 0) {
         uint32_t cur[17];
@@ -175,7 +175,7 @@ __device__ void sha256_range(const uint8_t *frame, uint64_t a, uint64_t b, uint6
     }
     // Remaining full blocks, byte by byte.
     for (uint64_t k = nfast; k < nfull; ++k) {
-        const uint8_t *p = frame + a + 64 * k;
+        const VC_GLOBAL uint8_t *p = frame + a + 64 * k;
 #pragma unroll
         for (int m = 0; m < 16; ++m) W[m] = load_be_bytes(p + 4 * m);
         sha_compress(H, W);
@@ -183,7 +183,7 @@ __device__ void sha256_range(const uint8_t *frame, uint64_t a, uint64_t b, uint6
     // Padding (FIPS 180-4 sec. 5.1.1): tail bytes, 0x80, zeros, 64-bit
     // big-endian bit length; one or two blocks.
     const uint32_t rem = static_cast<uint32_t>(len - 64 * nfull);
-    const uint8_t *p = frame + a + 64 * nfull;
+    const VC_GLOBAL uint8_t *p = frame + a + 64 * nfull;
     const uint64_t bits = len * 8;
     const int blocks = (rem + 9 <= 64) ? 1 : 2;
     for (int blk = 0; blk < blocks; ++blk) {
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(kShaMaxThreads) void sha256_subframes(const FrameDe
     if (lf < frames_per_group && f < count) {
         const FrameDesc d = desc[f];
         const uint64_t a = (d.L * sub) / n, b = (d.L * (sub + 1)) / n;
-        sha256_range(d.in, a, b, d.L, H);
+        sha256_range(gmem(d.in), a, b, d.L, H);
     }
 #pragma unroll
     for (int k = 0; k < 8; ++k) dig[tid][k] = H[k];
@@ -237,7 +237,7 @@ __global__ __launch_bounds__(kShaMaxThreads) void sha256_subframes(const FrameDe
         if (f2 >= count) break;
         uint32_t x = 0;
         for (uint32_t i = 0; i < n; ++i) x ^= dig[lf2 * n + i][word];
-        uint8_t *out = desc[f2].hash + 4 * word;
+        VC_GLOBAL uint8_t *out = gmem(desc[f2].hash) + 4 * word;
         out[0] = uint8_t(x >> 24);
         out[1] = uint8_t(x >> 16);
         out[2] = uint8_t(x >> 8);
