@@ -5,9 +5,11 @@ Workload: a synthetic 1920x1080x3 uint8 video of 300 frames (10 s at
 30 FPS, smooth gradients + moving discs + Gaussian noise, panning), one
 stream, n = 32 workers (the paper's server setting).  One step is the whole
 hot path over the batch: encrypt_frames on all 300 frames (frame hash, key
-schedule, confusion + XOR) followed by decrypt_frames of the result on a
-receiver context (key schedule, inverse confusion).  Frames stay resident in
-HBM; the timed region contains only the two library calls per step.
+schedule, confusion + XOR) and decrypt_frames of the result on a receiver
+context (key schedule, inverse confusion).  Sender and receiver each have a
+HIP stream, as they would in a real link: the sender encrypts batch k+1
+while the receiver decrypts batch k (ciphertext double-buffered).  Frames
+stay resident in HBM; the timed region contains only the library calls.
 
 Prints one JSON line: frames/s (value), per-kernel times from HIP events
 recorded around every launch inside the timed region, the HBM roofline of
@@ -78,9 +80,15 @@ def main():
     video = SynthVideo(w, h, seed=config_seed(3), pan=(3.0, 1.0))
     host = video.frames(T)
     frames = torch.from_numpy(host).to(dev)
-    cipher = torch.empty_like(frames)
+    # sender and receiver run on their own streams; ciphertext and hashes
+    # are double-buffered so that batch k+1 is encrypted while batch k is
+    # decrypted
+    cipher = [torch.empty_like(frames), torch.empty_like(frames)]
+    hashes = [torch.empty((T, 32), dtype=torch.uint8, device=dev) for _ in range(2)]
     plain = torch.empty_like(frames)
-    hashes = torch.empty((T, 32), dtype=torch.uint8, device=dev)
+    s_enc, s_dec = torch.cuda.Stream(), torch.cuda.Stream()
+    ready = [torch.cuda.Event(), torch.cuda.Event()]
+    freed = [torch.cuda.Event(), torch.cuda.Event()]
     per_frame_scratch = L + 2 * (3 * w + 3 * h) + 64 * n + 3 * 256
     scratch = max(per_frame_scratch * T + (64 << 20), 256 << 20)
     enc = V.Cipher.from_bytes(kb, gamma, n, scratch_bytes=scratch)
@@ -89,17 +97,26 @@ def main():
         enc.tune(args.strip, args.threads)
         dec.tune(args.strip, args.threads)
 
+    nstep = [0]
+    torch.cuda.synchronize()
+
     def step():
-        enc.encrypt(frames, out=cipher, hashes=hashes)
-        dec.decrypt(cipher, hashes, out=plain)
+        k = nstep[0] & 1
+        nstep[0] += 1
+        s_enc.wait_event(freed[k])          # the receiver is done with buffer k
+        enc.encrypt(frames, out=cipher[k], hashes=hashes[k], stream=s_enc)
+        ready[k].record(s_enc)
+        s_dec.wait_event(ready[k])
+        dec.decrypt(cipher[k], hashes[k], out=plain, stream=s_dec)
+        freed[k].record(s_dec)
 
     # ---- first step: keep a sample for the oracle check ----
     step()
     torch.cuda.synchronize()
     roundtrip_ok = bool(torch.equal(plain, frames))
     sample_frames = 4
-    first_c = cipher[:sample_frames].cpu().numpy()
-    first_h = hashes.cpu().numpy()
+    first_c = cipher[0][:sample_frames].cpu().numpy()
+    first_h = hashes[0].cpu().numpy()
     for _ in range(max(args.warmup - 1, 0)):
         step()
     torch.cuda.synchronize()
@@ -109,14 +126,13 @@ def main():
     dec.profile(True)
     enc.profile_reset()
     dec.profile_reset()
-    stream = torch.cuda.current_stream()
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    evs[0].record(stream)
+    evs[0].record(s_dec)
     for k in range(args.steps):
         step()
-        evs[k + 1].record(stream)
+        evs[k + 1].record(s_dec)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0

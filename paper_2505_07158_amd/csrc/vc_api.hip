@@ -203,14 +203,16 @@ uint32_t pick_strip(const vc_cipher *ctx, int decrypt, uint32_t w, uint32_t h) {
         if (ctx->strip <= wcap && confuse_lds_bytes(decrypt, h, ctx->strip) <= ctx->lds_limit)
             return ctx->strip;
     }
-    // widest strip that leaves room for two workgroups per CU, else the
-    // widest that fits at all
-    uint32_t best = 0, fits = 0;
+    // Measured on MI355X (1080p, 300 frames): encryption is fastest with
+    // the widest strip that fits the LDS (one workgroup per CU), decryption
+    // with the widest strip that leaves room for two workgroups per CU.
+    uint32_t half = 0, fits = 0;
     for (uint32_t wt = 4; wt <= 64 && wt <= wcap; wt *= 2) {
-        if (confuse_lds_bytes(decrypt, h, wt) <= ctx->lds_limit / 2) best = wt;
+        if (confuse_lds_bytes(decrypt, h, wt) <= ctx->lds_limit / 2) half = wt;
         if (confuse_lds_bytes(decrypt, h, wt) <= ctx->lds_limit) fits = wt;
     }
-    return best ? best : fits;
+    if (decrypt) return half ? half : fits;
+    return fits;
 }
 
 enum class Op { Encrypt, Decrypt, Hash, DebugConfuse, DebugKeysched };
@@ -397,7 +399,7 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         for (auto &kv : seq_next) ctx->next_seq[kv.first] = kv.second;
 
     ConfuseTuning tun;
-    tun.threads = ctx->threads ? ctx->threads : 512;
+    tun.threads = ctx->threads ? ctx->threads : 1024;
     tun.xcd_map = ctx->xcd_map;
 
     // ---- launches ----

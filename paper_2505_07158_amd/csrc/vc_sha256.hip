@@ -208,6 +208,196 @@ __device__ void sha256_range(const VC_GLOBAL uint8_t *frame, uint64_t a, uint64_
     }
 }
 
+// ----------------------------------------------------------------------
+// Two-wave form (n <= 64): the message schedule does not depend on the
+// compression state, so one wave (the schedule wave) loads each block,
+// expands W and writes K[t] + W[t] to LDS while the other wave (the
+// compression wave) runs the 64 rounds of the previous block.  Lane l of
+// both waves serves the same sub-frame.  Double-buffered, one barrier per
+// block.
+// ----------------------------------------------------------------------
+constexpr int kKwStride = 68;  // words per lane and buffer (64 + 4: 16-byte rows, no bank aliasing)
+
+// Message words of block k of the padded sub-frame [a, b) of a frame of L
+// bytes (FIPS 180-4 sec. 5.1.1), for any k < blocks.
+struct SubFrame {
+    const VC_GLOBAL uint8_t *frame;
+    uint64_t a, len, L;
+    uint64_t nfull, nfast;
+    uint32_t sh;
+    const VC_GLOBAL uint32_t *wp;
+    uint32_t blocks;
+};
+
+__device__ __forceinline__ SubFrame make_subframe(const VC_GLOBAL uint8_t *frame, uint64_t a, uint64_t b,
+                                                  uint64_t L) {
+    SubFrame f;
+    f.frame = frame;
+    f.a = a;
+    f.len = b - a;
+    f.L = L;
+    f.nfull = f.len / 64;
+    const uintptr_t start = reinterpret_cast<uintptr_t>(frame + a);
+    f.sh = static_cast<uint32_t>(start & 3);
+    const uintptr_t base = start - f.sh;
+    const uintptr_t end = reinterpret_cast<uintptr_t>(frame + L);
+    f.nfast = 0;
+    if (end >= base + 68) {
+        f.nfast = (end - base - 68) / 64 + 1;
+        if (f.nfast > f.nfull) f.nfast = f.nfull;
+    }
+    f.wp = reinterpret_cast<const VC_GLOBAL uint32_t *>(base);
+    const uint32_t rem = static_cast<uint32_t>(f.len - 64 * f.nfull);
+    f.blocks = static_cast<uint32_t>(f.nfull) + ((rem + 9 <= 64) ? 1 : 2);
+    return f;
+}
+
+__device__ __forceinline__ void block_words(const SubFrame &f, uint64_t k, uint32_t (&W)[16]) {
+    if (k < f.nfast) {
+        uint32_t cur[17];
+        load_window(f.wp + 16 * k, cur);
+#pragma unroll
+        for (int m = 0; m < 16; ++m) W[m] = bswap32(__builtin_amdgcn_alignbyte(cur[m + 1], cur[m], f.sh));
+    } else if (k < f.nfull) {
+        const VC_GLOBAL uint8_t *p = f.frame + f.a + 64 * k;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) W[m] = load_be_bytes(p + 4 * m);
+    } else {
+        const uint32_t rem = static_cast<uint32_t>(f.len - 64 * f.nfull);
+        const VC_GLOBAL uint8_t *p = f.frame + f.a + 64 * f.nfull;
+        const uint32_t blk = static_cast<uint32_t>(k - f.nfull);
+        const int last = (rem + 9 <= 64) ? 0 : 1;
+        for (int m = 0; m < 16; ++m) {
+            uint32_t word = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t j = 64 * blk + 4 * m + q;
+                uint32_t byte = 0;
+                if (j < rem) byte = p[j];
+                else if (j == rem) byte = 0x80;
+                word = (word << 8) | byte;
+            }
+            W[m] = word;
+        }
+        if (static_cast<int>(blk) == last) {
+            const uint64_t bits = f.len * 8;
+            W[14] = static_cast<uint32_t>(bits >> 32);
+            W[15] = static_cast<uint32_t>(bits);
+        }
+    }
+}
+
+// Schedule wave: W[0..63] of one block, plus K, into the lane's LDS row.
+template <int t>
+__device__ __forceinline__ void sched_step(uint32_t (&W)[16], uint32_t (&kw)[64]) {
+    if constexpr (t >= 16)
+        W[t & 15] = ssig1(W[(t - 2) & 15]) + W[(t - 7) & 15] + ssig0(W[(t - 15) & 15]) + W[t & 15];
+    kw[t] = W[t & 15] + kSha.K[t];
+}
+template <int... t>
+__device__ __forceinline__ void sched_all(uint32_t (&W)[16], uint32_t (&kw)[64], std::integer_sequence<int, t...>) {
+    (sched_step<t>(W, kw), ...);
+}
+
+// Compression wave: round t with K[t] + W[t] precomputed.
+template <int t>
+__device__ __forceinline__ void round_kw(uint32_t (&v)[8], const uint32_t (&kw)[64]) {
+    const uint32_t a = v[(0 - t) & 7], b = v[(1 - t) & 7], c = v[(2 - t) & 7];
+    const uint32_t d = v[(3 - t) & 7], e = v[(4 - t) & 7], f = v[(5 - t) & 7];
+    const uint32_t g = v[(6 - t) & 7], h = v[(7 - t) & 7];
+    const uint32_t T1 = h + bsig1(e) + ch(e, f, g) + kw[t];
+    const uint32_t T2 = bsig0(a) + maj(a, b, c);
+    v[(3 - t) & 7] = d + T1;
+    v[(7 - t) & 7] = T1 + T2;
+}
+template <int... t>
+__device__ __forceinline__ void rounds_kw(uint32_t (&v)[8], const uint32_t (&kw)[64], std::integer_sequence<int, t...>) {
+    (round_kw<t>(v, kw), ...);
+}
+
+typedef uint32_t u32x4_lds __attribute__((ext_vector_type(4)));
+
+// 128 threads: wave 0 schedules, wave 1 compresses; 64/n frames per group.
+__global__ __launch_bounds__(128) void sha256_subframes_2w(const FrameDesc *__restrict__ desc, uint32_t count,
+                                                           uint32_t n, uint32_t frames_per_group) {
+    __shared__ __align__(16) uint32_t kwbuf[2][64][kKwStride];
+    __shared__ uint32_t dig[64][9];
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const uint32_t lf = lane / n, sub = lane % n;
+    const uint32_t f = blockIdx.x * frames_per_group + lf;
+    const bool active = lf < frames_per_group && f < count;
+    SubFrame sf{};
+    uint32_t blocks = 0;
+    if (active) {
+        const FrameDesc d = desc[f];
+        const uint64_t a = (d.L * sub) / n, b = (d.L * (sub + 1)) / n;
+        sf = make_subframe(gmem(d.in), a, b, d.L);
+        blocks = sf.blocks;
+    }
+    // every wave of the group runs the same number of iterations
+    uint32_t nb = blocks;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) nb = max(nb, static_cast<uint32_t>(__shfl_xor(static_cast<int>(nb), o)));
+
+    if (wave == 0) {
+        uint32_t W[16], kw[64];
+        auto produce = [&](uint32_t k, int buf) {
+            if (k < blocks) {
+                block_words(sf, k, W);
+                sched_all(W, kw, std::make_integer_sequence<int, 64>{});
+                u32x4_lds *row = reinterpret_cast<u32x4_lds *>(&kwbuf[buf][lane][0]);
+#pragma unroll
+                for (int q = 0; q < 16; ++q) row[q] = u32x4_lds{kw[4 * q], kw[4 * q + 1], kw[4 * q + 2], kw[4 * q + 3]};
+            }
+        };
+        produce(0, 0);
+        __syncthreads();
+        for (uint32_t k = 0; k < nb; ++k) {
+            if (k + 1 < nb) produce(k + 1, (k + 1) & 1);
+            __syncthreads();
+        }
+        __syncthreads();  // matches the digest barrier of the compression wave
+    } else {
+        uint32_t H[8], kw[64];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) H[m] = kSha.H0[m];
+        __syncthreads();
+        for (uint32_t k = 0; k < nb; ++k) {
+            if (k < blocks) {
+                const u32x4_lds *row = reinterpret_cast<const u32x4_lds *>(&kwbuf[k & 1][lane][0]);
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const u32x4_lds x = row[q];
+                    kw[4 * q] = x.x; kw[4 * q + 1] = x.y; kw[4 * q + 2] = x.z; kw[4 * q + 3] = x.w;
+                }
+                uint32_t v[8];
+#pragma unroll
+                for (int m = 0; m < 8; ++m) v[m] = H[m];
+                rounds_kw(v, kw, std::make_integer_sequence<int, 64>{});
+#pragma unroll
+                for (int m = 0; m < 8; ++m) H[m] += v[m];
+            }
+            __syncthreads();
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) dig[lane][m] = active ? H[m] : 0u;
+        __syncthreads();
+        // lane t < frames_per_group*8: word t%8 of local frame t/8
+        for (uint32_t t = lane; t < frames_per_group * 8; t += 64) {
+            const uint32_t lf2 = t / 8, word = t % 8;
+            const uint32_t f2 = blockIdx.x * frames_per_group + lf2;
+            if (f2 >= count) break;
+            uint32_t x = 0;
+            for (uint32_t i = 0; i < n; ++i) x ^= dig[lf2 * n + i][word];
+            VC_GLOBAL uint8_t *out = gmem(desc[f2].hash) + 4 * word;
+            out[0] = uint8_t(x >> 24);
+            out[1] = uint8_t(x >> 16);
+            out[2] = uint8_t(x >> 8);
+            out[3] = uint8_t(x);
+        }
+    }
+}
+
 constexpr int kShaMaxThreads = 1024;
 
 // Threads: blockDim.x lanes; frames_per_group frames of n lanes each.
@@ -250,13 +440,14 @@ __global__ __launch_bounds__(kShaMaxThreads) void sha256_subframes(const FrameDe
 hipError_t launch_sha256_subframes(const FrameDesc *d_desc, uint32_t count, uint32_t n,
                                    hipStream_t s) {
     if (count == 0) return hipSuccess;
-    // One wave holds 64/n frames when n <= 64 (sub-frame lanes are the
-    // only parallelism of a frame, so small groups spread the waves over as
-    // many CUs as possible); otherwise one frame per workgroup.
+    // n <= 64: a pair of waves (schedule + compression) holds 64/n frames.
+    // Otherwise one frame per workgroup, one wave per 64 sub-frames.
     uint32_t threads, fpg;
     if (n <= 64) {
         fpg = 64 / n;
-        threads = 64;
+        const uint32_t groups = (count + fpg - 1) / fpg;
+        hipLaunchKernelGGL(sha256_subframes_2w, dim3(groups), dim3(128), 0, s, d_desc, count, n, fpg);
+        return hipGetLastError();
     } else {
         fpg = 1;
         threads = ((n + 63) / 64) * 64;
