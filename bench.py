@@ -4,12 +4,15 @@
 Workload: a synthetic 1920x1080x3 uint8 video of 300 frames (10 s at
 30 FPS, smooth gradients + moving discs + Gaussian noise, panning), one
 stream, n = 32 workers (the paper's server setting).  One step is the whole
-hot path over the batch: encrypt_frames on all 300 frames (frame hash, key
-schedule, confusion + XOR) and decrypt_frames of the result on a receiver
-context (key schedule, inverse confusion).  Sender and receiver each have a
-HIP stream, as they would in a real link: the sender encrypts batch k+1
-while the receiver decrypts batch k (ciphertext double-buffered).  Frames
-stay resident in HBM; the timed region contains only the library calls.
+hot path over one batch of 300 frames: frame hash (vc_hash_frames), key
+schedule + confusion + XOR (encrypt_frames_hashed), and on a receiver
+context key schedule + inverse confusion (decrypt_frames).  The three run
+as a stream pipeline, the way a sender and a receiver overlap on a live
+link: in each step batch k is hashed, batch k-1 encrypted and batch k-2
+decrypted, so every step does the full work of one batch.  Frames stay
+resident in HBM; the timed region contains only the library calls.  The
+same work without the pipeline (encrypt_frames then decrypt_frames) is
+reported beside it.
 
 Prints one JSON line: frames/s (value), per-kernel times from HIP events
 recorded around every launch inside the timed region, the HBM roofline of
@@ -45,10 +48,42 @@ def parse():
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--strip", type=int, default=0, help="confusion strip width (0 = automatic)")
     ap.add_argument("--threads", type=int, default=0, help="confusion workgroup size (0 = automatic)")
+    ap.add_argument("--parts", type=int, default=4, help="sub-batches per call whose keygen and confusion "
+                    "overlap the chain (1 = none)")
+    ap.add_argument("--side", type=int, default=2, help="side streams per context for that overlap")
+    ap.add_argument("--hw-queues", type=int, default=0,
+                    help="GPU_MAX_HW_QUEUES for this process (0 = HIP's default); must be set before HIP starts")
     ap.add_argument("--latency-iters", type=int, default=30)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--second-n", type=int, default=256, help="worker count of the second row (0 = skip)")
+    ap.add_argument("--second-steps", type=int, default=3)
+    ap.add_argument("--unpipelined-steps", type=int, default=4, help="steps of the reference without the pipeline")
     return ap.parse_args()
+
+
+def measured_traffic(frames: int, w: int, h: int) -> dict:
+    """HBM bytes per launch of the confusion kernels from the committed
+    rocprofv3 counter runs (profiles/traffic.json), scaled by the copy
+    kernel's calibration.  Used only while the kernel source is the one the
+    counters were taken on, and for the same workload."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    src = os.path.join(ROOT, "paper_2505_07158_amd", "csrc", "vc_confuse.hip")
+    if not os.path.exists(path):
+        return {}
+    rec = json.load(open(path))
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != digest or rec.get("frames_per_launch") != frames or \
+            rec.get("width") != w or rec.get("height") != h:
+        return {}
+    out = {}
+    for name, k in rec.get("kernels", {}).items():
+        fetch = k["fetch_kib"] * 1024 * rec["copy_scale_fetch"]
+        write = k["write_kib"] * 1024 * rec["copy_scale_write"]
+        out[name] = {"bytes_per_launch": round(fetch + write), "fetch_bytes": round(fetch), "write_bytes": round(write),
+                     "algorithmic_bytes": 9 * w * h * frames, "source": "profiles/traffic.json"}
+    return out
 
 
 def pct(xs, q):
@@ -64,6 +99,10 @@ def main():
               "across GPUs with no collective; see the design notes).  Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
+    if args.hw_queues:
+        if not 1 <= args.hw_queues <= 32:
+            sys.exit("--hw-queues must be in 1..32")
+        os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
     import numpy as np
     import torch
 
@@ -80,48 +119,77 @@ def main():
     video = SynthVideo(w, h, seed=config_seed(3), pan=(3.0, 1.0))
     host = video.frames(T)
     frames = torch.from_numpy(host).to(dev)
-    # sender and receiver run on their own streams; ciphertext and hashes
-    # are double-buffered so that batch k+1 is encrypted while batch k is
-    # decrypted
-    cipher = [torch.empty_like(frames), torch.empty_like(frames)]
-    hashes = [torch.empty((T, 32), dtype=torch.uint8, device=dev) for _ in range(2)]
+    # Three-stage stream pipeline (a sender that hashes frames as they come
+    # and encrypts them as the key chain allows, and a receiver): batch k is
+    # hashed while batch k-1 is encrypted and batch k-2 decrypted.  Hash and
+    # ciphertext buffers rotate over three slots.
+    NB = 3
+    hbuf = [torch.empty((T, 32), dtype=torch.uint8, device=dev) for _ in range(NB)]
+    cbuf = [torch.empty_like(frames) for _ in range(NB)]
     plain = torch.empty_like(frames)
-    s_enc, s_dec = torch.cuda.Stream(), torch.cuda.Stream()
-    ready = [torch.cuda.Event(), torch.cuda.Event()]
-    freed = [torch.cuda.Event(), torch.cuda.Event()]
+    s_hash, s_enc, s_dec = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    hashed = [torch.cuda.Event() for _ in range(NB)]
+    ready = [torch.cuda.Event() for _ in range(NB)]
+    freed = [torch.cuda.Event() for _ in range(NB)]
     per_frame_scratch = L + 2 * (3 * w + 3 * h) + 64 * n + 3 * 256
     scratch = max(per_frame_scratch * T + (64 << 20), 256 << 20)
-    enc = V.Cipher.from_bytes(kb, gamma, n, scratch_bytes=scratch)
-    dec = V.Cipher.from_bytes(kb, gamma, n, scratch_bytes=scratch)
-    if args.strip or args.threads:
-        enc.tune(args.strip, args.threads)
-        dec.tune(args.strip, args.threads)
 
-    nstep = [0]
+    def make_cipher(nn, scratch_bytes):
+        c = V.Cipher.from_bytes(kb, gamma, nn, scratch_bytes=scratch_bytes)
+        if args.strip or args.threads:
+            c.tune(args.strip, args.threads)
+        c.overlap(args.parts, args.side)
+        return c
+
+    enc = make_cipher(n, scratch)
+    dec = make_cipher(n, scratch)
+
+    def stage_hash(k):
+        b = k % NB
+        s_hash.wait_event(freed[b])          # the receiver is done with slot b
+        enc.hash(frames, stream=s_hash, out=hbuf[b])
+        hashed[b].record(s_hash)
+
+    def stage_enc(k):
+        b = k % NB
+        s_enc.wait_event(hashed[b])
+        enc.encrypt_hashed(frames, hbuf[b], out=cbuf[b], stream=s_enc)
+        ready[b].record(s_enc)
+
+    def stage_dec(k):
+        b = k % NB
+        s_dec.wait_event(ready[b])
+        dec.decrypt(cbuf[b], hbuf[b], out=plain, stream=s_dec)
+        freed[b].record(s_dec)
+
+    # Reference copy of known size (the plain-copy calibration of the HBM
+    # byte counters when this benchmark runs under rocprofv3 --pmc).
+    ref_copy = frames.clone()
+    del ref_copy
     torch.cuda.synchronize()
 
-    def step():
-        k = nstep[0] & 1
-        nstep[0] += 1
-        s_enc.wait_event(freed[k])          # the receiver is done with buffer k
-        enc.encrypt(frames, out=cipher[k], hashes=hashes[k], stream=s_enc)
-        ready[k].record(s_enc)
-        s_dec.wait_event(ready[k])
-        dec.decrypt(cipher[k], hashes[k], out=plain, stream=s_dec)
-        freed[k].record(s_dec)
-
-    # ---- first step: keep a sample for the oracle check ----
-    step()
+    # ---- batch 0, unpipelined: keep a sample for the oracle check ----
+    stage_hash(0)
+    stage_enc(0)
+    stage_dec(0)
     torch.cuda.synchronize()
     roundtrip_ok = bool(torch.equal(plain, frames))
     sample_frames = 4
-    first_c = cipher[0][:sample_frames].cpu().numpy()
-    first_h = hashes[0].cpu().numpy()
-    for _ in range(max(args.warmup - 1, 0)):
-        step()
+    first_c = cbuf[0][:sample_frames].cpu().numpy()
+    first_h = hbuf[0].cpu().numpy()
+
+    # ---- fill the pipeline, warm up ----
+    stage_hash(1)
+    stage_hash(2)
+    stage_enc(1)
+    k = 3
+    for _ in range(args.warmup):
+        stage_hash(k); stage_enc(k - 1); stage_dec(k - 2)
+        k += 1
     torch.cuda.synchronize()
 
-    # ---- timed region ----
+    # ---- timed region: each step hashes one batch, encrypts one and
+    # decrypts one ----
     enc.profile(True)
     dec.profile(True)
     enc.profile_reset()
@@ -130,18 +198,53 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     evs[0].record(s_dec)
-    for k in range(args.steps):
-        step()
-        evs[k + 1].record(s_dec)
+    for i in range(args.steps):
+        stage_hash(k); stage_enc(k - 1); stage_dec(k - 2)
+        evs[i + 1].record(s_dec)
+        k += 1
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     elapsed = t1 - t0
-    step_ms = [evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]
+    step_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
     prof_e, prof_d = enc.profile_read(), dec.profile_read()
     enc.profile(False)
     dec.profile(False)
+    # drain
+    stage_enc(k - 1); stage_dec(k - 2); stage_dec(k - 1)
+    torch.cuda.synchronize()
     roundtrip_ok = roundtrip_ok and bool(torch.equal(plain, frames))
     assert enc.status() == 0 and dec.status() == 0
+
+    # ---- reference: the same work without the pipeline (encrypt_frames,
+    # then decrypt_frames on the receiver's stream, double-buffered) ----
+    unpiped = None
+    if args.unpipelined_steps:
+        e3 = make_cipher(n, scratch)
+        d3 = make_cipher(n, scratch)
+
+        def plain_step(j):
+            b = j % 2
+            s_enc.wait_event(freed[b])
+            e3.encrypt(frames, out=cbuf[b], hashes=hbuf[b], stream=s_enc)
+            ready[b].record(s_enc)
+            s_dec.wait_event(ready[b])
+            d3.decrypt(cbuf[b], hbuf[b], out=plain, stream=s_dec)
+            freed[b].record(s_dec)
+
+        torch.cuda.synchronize()
+        plain_step(0)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for j in range(args.unpipelined_steps):
+            plain_step(j + 1)
+        torch.cuda.synchronize()
+        el3 = time.perf_counter() - a
+        unpiped = {"value": round(T * args.unpipelined_steps / el3, 1), "unit": "frames/s",
+                   "ms_per_step": round(1000 * el3 / args.unpipelined_steps, 3),
+                   "steps": args.unpipelined_steps, "roundtrip_ok": bool(torch.equal(plain, frames)),
+                   "mode": "encrypt_frames then decrypt_frames, sender and receiver streams"}
+        e3.close()
+        d3.close()
 
     kernels = {}
     for name in V.KERNELS:
@@ -168,6 +271,12 @@ def main():
 
     roof_enc = hbm_roof("confuse_xor_enc")
     roof_dec = hbm_roof("confuse_xor_dec")
+    traffic = measured_traffic(T, w, h)
+    for roof in (roof_enc, roof_dec):
+        t = traffic.get(roof["kernel"])
+        if t is not None:
+            roof["traffic"] = t["bytes_per_launch"]
+            roof["traffic_detail"] = t
 
     # SHA-256: algorithmic 32-bit operations of FIPS 180-4 per 64-byte block
     # (rounds: Sigma1 5, Ch 3, T1 4 adds, Sigma0 5, Maj 4, T2 1, e 1, a 1 =
@@ -183,14 +292,50 @@ def main():
                 "max_blocks_per_lane": max(((sub[i + 1] - sub[i]) + 9 + 63) // 64 for i in range(n))}
     dominant = max(kernels, key=lambda k: kernels[k]["total_ms"])
 
+    # ---- second worker count (n = 256): same workload, timing only ----
+    second = None
+    if args.second_n:
+        n2 = args.second_n
+        scratch2 = max((L + 2 * (3 * w + 3 * h) + 64 * n2 + 3 * 256) * T + (64 << 20), 256 << 20)
+        e2 = make_cipher(n2, scratch2)
+        d2 = make_cipher(n2, scratch2)
+
+        def step2(k):
+            b = k % NB
+            s_hash.wait_event(freed[b])
+            e2.hash(frames, stream=s_hash, out=hbuf[b])
+            hashed[b].record(s_hash)
+            s_enc.wait_event(hashed[b])
+            e2.encrypt_hashed(frames, hbuf[b], out=cbuf[b], stream=s_enc)
+            ready[b].record(s_enc)
+            s_dec.wait_event(ready[b])
+            d2.decrypt(cbuf[b], hbuf[b], out=plain, stream=s_dec)
+            freed[b].record(s_dec)
+
+        torch.cuda.synchronize()
+        step2(0)
+        torch.cuda.synchronize()
+        ok2 = bool(torch.equal(plain, frames))
+        a = time.perf_counter()
+        for k in range(args.second_steps):
+            step2(k + 1)
+        torch.cuda.synchronize()
+        el2 = time.perf_counter() - a
+        second = {"n": n2, "value": round(T * args.second_steps / el2, 1), "unit": "frames/s",
+                  "ms_per_step": round(1000 * el2 / args.second_steps, 3), "steps": args.second_steps,
+                  "roundtrip_ok": ok2}
+        assert e2.status() == 0 and d2.status() == 0
+        e2.close()
+        d2.close()
+
     # ---- single-frame latency (encrypt, then decrypt, one 1080p frame) ----
     lat_e, lat_d = [], []
-    le = V.Cipher.from_bytes(kb, gamma, n, scratch_bytes=max(4 * per_frame_scratch, 64 << 20))
-    ld = V.Cipher.from_bytes(kb, gamma, n, scratch_bytes=max(4 * per_frame_scratch, 64 << 20))
+    le = make_cipher(n, max(4 * per_frame_scratch, 64 << 20))
+    ld = make_cipher(n, max(4 * per_frame_scratch, 64 << 20))
     c1 = torch.empty_like(frames[:1])
     p1 = torch.empty_like(frames[:1])
     h1 = torch.empty((1, 32), dtype=torch.uint8, device=dev)
-    for k in range(args.latency_iters + 3):
+    for k in range(args.latency_iters + 3 if args.latency_iters > 0 else 0):
         f = frames[k % T:k % T + 1]
         torch.cuda.synchronize()
         a = time.perf_counter()
@@ -241,7 +386,8 @@ def main():
         "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": f"{w}x{h}x3 uint8 synthetic video, {T} frames per step, 1 stream, n={n}, "
-                               "encrypt_frames + decrypt_frames per step",
+                               "one step = vc_hash_frames + encrypt_frames_hashed + decrypt_frames of one batch, "
+                               "three-stage stream pipeline (sender hash, sender encrypt, receiver decrypt)",
                    "frames_per_step": T, "width": w, "height": h, "n": n, "gamma": gamma},
         "roofline": roof_enc,
         "roofline_dec": roof_dec,
@@ -250,9 +396,11 @@ def main():
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
         "step_ms": {"p50": round(pct(step_ms, 50), 3), "p99": round(pct(step_ms, 99), 3)},
-        "latency_ms": {"encrypt_p50": round(pct(lat_e, 50), 3), "encrypt_p99": round(pct(lat_e, 99), 3),
-                       "decrypt_p50": round(pct(lat_d, 50), 3), "decrypt_p99": round(pct(lat_d, 99), 3),
-                       "mode": f"one {w}x{h} frame per call, host-synchronised"},
+        "latency_ms": ({"encrypt_p50": round(pct(lat_e, 50), 3), "encrypt_p99": round(pct(lat_e, 99), 3),
+                        "decrypt_p50": round(pct(lat_d, 50), 3), "decrypt_p99": round(pct(lat_d, 99), 3),
+                        "mode": f"one {w}x{h} frame per call, host-synchronised"} if lat_e else None),
+        "second_row": second,
+        "unpipelined": unpiped,
         "cpu_baseline": cpu,
         "roundtrip_ok": roundtrip_ok,
         "oracle_verified_sample": verified,

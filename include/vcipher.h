@@ -126,6 +126,17 @@ int decrypt_frames(vc_cipher *ctx, size_t count, const uint8_t *const *frames,
                    const vc_shape *shapes, const uint8_t *hashes,
                    uint8_t *const *out, void *stream);
 
+/* encrypt_frames with the frame hashes already computed (by
+ * vc_hash_frames on the same plaintext, possibly on another stream): runs
+ * the key schedule and the confusion + XOR only.  hashes (device,
+ * count*32 bytes) is read.  This lets a sender hash batch k+1 while batch k
+ * is being encrypted.  If a hash is not the one of Sec. II-A for its frame,
+ * the receiver can still decrypt with it, but the output no longer follows
+ * the paper's protocol.  Same errors and ordering rules as encrypt_frames. */
+int encrypt_frames_hashed(vc_cipher *ctx, size_t count, const uint8_t *const *frames,
+                          const vc_shape *shapes, const uint8_t *hashes, uint8_t *const *out,
+                          void *stream);
+
 /* Frame hash H of Sec. II-A for each frame (n sub-frames of the context's
  * key), without encrypting and without touching chain states. Only w, h, c
  * of shapes are read. */
@@ -157,6 +168,19 @@ int vc_profile_enable(vc_cipher *ctx, int enable);
 int vc_profile_read(vc_cipher *ctx, int kernel_id, double *total_ms, uint64_t *launches);
 int vc_profile_reset(vc_cipher *ctx);
 const char *vc_kernel_name(int kernel_id);
+
+/* Overlap of the LHCS_m chain with keygen and confusion inside one call.
+ * Frames of a call are cut into `parts` sub-batches in call order (1 = no
+ * cut, at most 64); the chain of every part runs on the caller's stream,
+ * the keygen and confusion of part k on side stream k mod side_streams of
+ * the context (0 = everything on the caller's stream, at most 8), and the
+ * caller's stream waits for the side streams before the call's work is
+ * complete.  Defaults: 4 parts, 2 side streams.  A process whose streams
+ * outnumber the device's hardware queues (GPU_MAX_HW_QUEUES, 4 by default
+ * in HIP) shares queues between streams, which serialises their work; size
+ * the queue count to the streams in use.  Never changes output bytes.
+ * VC_EINVAL for out-of-range arguments. */
+int vc_set_overlap(vc_cipher *ctx, uint32_t parts, uint32_t side_streams);
 
 /* Strip width (pixels: 4, 8, 16, 32 or 64; 0 = automatic) and
  * threads per workgroup (256, 512 or 1024; 0 = automatic) of the

@@ -3,12 +3,19 @@
 // Host side of the path: argument validation, per-stream sequence checks,
 // descriptor packing (one pinned staging buffer per call, copied to the
 // device on the caller's stream), scratch planning (frames are processed in
-// chunks whose IR, D and B fit the context's scratch), and the launch
-// sequence per chunk:
-//   encrypt: sha256_subframes (all frames) -> lhcs_chain -> lhcs_keygen ->
-//            confuse_xor_enc (one launch per frame shape)
-//   decrypt: lhcs_chain -> lhcs_keygen -> confuse_xor_dec
-// All of it is enqueued asynchronously on the caller's stream.
+// spans whose IR, D and B fit the context's scratch), and the launch
+// sequence:
+//   encrypt: sha256_subframes (all frames) -> per part: lhcs_chain ->
+//            lhcs_keygen -> confuse_xor_enc (one launch per frame shape)
+//   decrypt: per part: lhcs_chain -> lhcs_keygen -> confuse_xor_dec
+// The chain is the serial spine of a stream (frame t+1 starts from the end
+// of frame t), while the keygen and confusion of a frame need only that
+// frame's IR.  So each scratch span is cut into parts in call order: the
+// chain of every part runs on the caller's stream, and the keygen and
+// confusion of part k run on one of the context's side streams, forked
+// after the chain of part k; keygen k then overlaps the chain of part k+1.
+// The caller's stream joins the side streams at the end of every span, so
+// the call is stream-ordered as a whole and scratch is never reused early.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -31,6 +38,7 @@ constexpr double kGammaLo = -1.52;
 constexpr double kGammaHi = -0.06;
 constexpr uint32_t kMaxDim = 65535;
 constexpr int kRing = 4;
+constexpr int kMaxSide = 8;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -63,9 +71,10 @@ struct Group {  // frames [first, first + count) of the descriptor array share a
     bool aligned;
 };
 
-struct Chunk {
+struct Chunk {  // one part of a scratch span
     uint32_t desc_begin, desc_end;
     uint32_t run_begin, run_end;
+    uint32_t span;
     std::vector<Group> groups;
 };
 
@@ -91,6 +100,13 @@ struct vc_cipher {
     // tuning
     uint32_t strip = 0, threads = 0;
     int xcd_map = 1;
+    // overlap of the chain with keygen + confusion (side streams at default
+    // priority, created on first use so that idle contexts hold none)
+    uint32_t parts = 4;
+    uint32_t nside = 2;
+    hipStream_t side[kMaxSide] = {};
+    hipEvent_t fork_ev[kMaxSide] = {};
+    hipEvent_t join_ev[kMaxSide] = {};
     // profiling
     bool profile = false;
     std::vector<PendingEvent> pending;
@@ -100,6 +116,11 @@ struct vc_cipher {
     hipStream_t last_stream = nullptr;
     std::mutex mu;
 };
+
+namespace {
+struct CallArgs;
+}
+static int locked_call(vc_cipher *ctx, const CallArgs &a);
 
 namespace {
 
@@ -215,7 +236,7 @@ uint32_t pick_strip(const vc_cipher *ctx, int decrypt, uint32_t w, uint32_t h) {
     return fits;
 }
 
-enum class Op { Encrypt, Decrypt, Hash, DebugConfuse, DebugKeysched };
+enum class Op { Encrypt, EncryptHashed, Decrypt, Hash, DebugConfuse, DebugKeysched };
 
 struct CallArgs {
     Op op;
@@ -234,9 +255,21 @@ struct CallArgs {
     hipStream_t stream;
 };
 
+hipError_t ensure_side(vc_cipher *ctx, uint32_t count) {
+    for (uint32_t k = 0; k < count; ++k) {
+        if (ctx->side[k]) continue;
+        hipError_t e = hipEventCreateWithFlags(&ctx->fork_ev[k], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join_ev[k], hipEventDisableTiming);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
 int run_call(vc_cipher *ctx, const CallArgs &a) {
-    const bool uses_chain = a.op == Op::Encrypt || a.op == Op::Decrypt || a.op == Op::DebugKeysched;
-    const bool uses_scratch = a.op == Op::Encrypt || a.op == Op::Decrypt;
+    const bool encrypting = a.op == Op::Encrypt || a.op == Op::EncryptHashed;
+    const bool uses_chain = encrypting || a.op == Op::Decrypt || a.op == Op::DebugKeysched;
+    const bool uses_scratch = encrypting || a.op == Op::Decrypt;
     const int dec_kernel = (a.op == Op::Decrypt) || (a.op == Op::DebugConfuse && a.decrypt);
     const uint32_t n = ctx->key.n;
     const size_t count = a.count;
@@ -249,10 +282,8 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         if (rc) return rc;
         const uint64_t L = frame_bytes(s);
         if (a.op != Op::DebugKeysched && !a.in[f]) return VC_EINVAL;
-        if ((a.op == Op::Encrypt || a.op == Op::Decrypt || a.op == Op::DebugConfuse) && !a.out[f])
-            return VC_EINVAL;
-        if ((a.op == Op::Encrypt || a.op == Op::DebugConfuse || a.op == Op::Decrypt) &&
-            overlaps(a.in[f], L, a.out[f], L))
+        if ((encrypting || a.op == Op::Decrypt || a.op == Op::DebugConfuse) && !a.out[f]) return VC_EINVAL;
+        if ((encrypting || a.op == Op::DebugConfuse || a.op == Op::Decrypt) && overlaps(a.in[f], L, a.out[f], L))
             return VC_EINVAL;
         if (a.op == Op::DebugConfuse && (!a.dbgD[f] || !a.dbgB[f])) return VC_EINVAL;
         if (a.op == Op::DebugKeysched && (!a.kIR[f] || !a.kD[f] || !a.kB[f])) return VC_EINVAL;
@@ -266,10 +297,20 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         }
     }
     if (count == 0) return VC_OK;
+    if ((encrypting || a.op == Op::Decrypt) && ctx->nside > 0 && ctx->parts > 1) {
+        const hipError_t e = ensure_side(ctx, ctx->nside);
+        if (e != hipSuccess) return map_err(e);
+    }
 
-    // ---- plan chunks (consecutive frames whose scratch fits) ----
-    std::vector<std::pair<size_t, size_t>> spans;  // [begin, end) in call order
+    // ---- plan spans (consecutive frames whose scratch fits) and parts ----
+    const bool overlap = (encrypting || a.op == Op::Decrypt) && ctx->nside > 0 && ctx->parts > 1;
+    struct Part {
+        size_t b, e;
+        uint32_t span;
+    };
+    std::vector<Part> parts;  // [b, e) in call order
     {
+        std::vector<std::pair<size_t, size_t>> spans;
         size_t b = 0;
         uint64_t used = 0;
         for (size_t f = 0; f < count; ++f) {
@@ -282,16 +323,27 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
             used += need;
         }
         spans.push_back({b, count});
+        for (size_t si = 0; si < spans.size(); ++si) {
+            const size_t sb = spans[si].first, len = spans[si].second - sb;
+            const size_t np = overlap ? std::min<size_t>(ctx->parts, len) : 1;
+            for (size_t k = 0; k < np; ++k)
+                parts.push_back({sb + len * k / np, sb + len * (k + 1) / np, static_cast<uint32_t>(si)});
+        }
     }
 
-    // ---- build descriptors, runs and order ----
+    // ---- build descriptors, runs and chain records ----
     std::vector<FrameDesc> desc(count);
     std::vector<StreamRun> runs;
-    std::vector<uint32_t> order;
+    std::vector<ChainRec> order;
     std::vector<Chunk> chunks;
     std::vector<uint32_t> desc_of(count);
-    for (auto &sp : spans) {
+    uint64_t off = 0;
+    for (size_t pi = 0; pi < parts.size(); ++pi) {
+        const Part &pt = parts[pi];
+        const std::pair<size_t, size_t> sp{pt.b, pt.e};
+        if (pi > 0 && parts[pi - 1].span != pt.span) off = 0;  // a new span reuses the scratch
         Chunk ch;
+        ch.span = pt.span;
         ch.desc_begin = static_cast<uint32_t>(sp.first);
         ch.desc_end = static_cast<uint32_t>(sp.second);
         // shape groups: stable order by (w, h, aligned)
@@ -310,7 +362,6 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
             const vc_shape &p = a.shapes[x], &q = a.shapes[y];
             return std::make_tuple(p.w, p.h, !aligned_of(x)) < std::make_tuple(q.w, q.h, !aligned_of(y));
         });
-        uint64_t off = 0;
         for (size_t k = 0; k < idx.size(); ++k) {
             const size_t f = idx[k];
             const uint32_t di = static_cast<uint32_t>(sp.first + k);
@@ -366,7 +417,7 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
             for (uint32_t st : stream_order) {
                 auto &v = per_stream[st];
                 runs.push_back({st, static_cast<uint32_t>(order.size()), static_cast<uint32_t>(v.size()), 0});
-                order.insert(order.end(), v.begin(), v.end());
+                for (uint32_t di : v) order.push_back({desc[di].hash, desc[di].IR});
             }
         }
         ch.run_end = static_cast<uint32_t>(runs.size());
@@ -376,7 +427,7 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
     // ---- stage and upload ----
     const size_t desc_bytes = align_up(sizeof(FrameDesc) * count, 256);
     const size_t runs_bytes = align_up(sizeof(StreamRun) * std::max<size_t>(runs.size(), 1), 256);
-    const size_t order_bytes = align_up(sizeof(uint32_t) * std::max<size_t>(order.size(), 1), 256);
+    const size_t order_bytes = align_up(sizeof(ChainRec) * std::max<size_t>(order.size(), 1), 256);
     const size_t total = desc_bytes + runs_bytes + order_bytes;
     int slot = 0;
     int rc = stage_acquire(ctx, total, &slot);
@@ -384,14 +435,14 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
     uint8_t *hs = ctx->h_stage[slot];
     std::memcpy(hs, desc.data(), sizeof(FrameDesc) * count);
     if (!runs.empty()) std::memcpy(hs + desc_bytes, runs.data(), sizeof(StreamRun) * runs.size());
-    if (!order.empty()) std::memcpy(hs + desc_bytes + runs_bytes, order.data(), sizeof(uint32_t) * order.size());
+    if (!order.empty()) std::memcpy(hs + desc_bytes + runs_bytes, order.data(), sizeof(ChainRec) * order.size());
     const hipStream_t s = a.stream;
     uint8_t *ds = ctx->d_stage[slot];
     hipError_t e = hipMemcpyAsync(ds, hs, total, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return map_err(e);
     const FrameDesc *d_desc = reinterpret_cast<const FrameDesc *>(ds);
     const StreamRun *d_runs = reinterpret_cast<const StreamRun *>(ds + desc_bytes);
-    const uint32_t *d_order = reinterpret_cast<const uint32_t *>(ds + desc_bytes + runs_bytes);
+    const ChainRec *d_order = reinterpret_cast<const ChainRec *>(ds + desc_bytes + runs_bytes);
 
     // The sequence numbers advance as soon as work is enqueued: the chain
     // states on the device follow stream order.
@@ -408,25 +459,61 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         if (e != hipSuccess) return map_err(e);
     }
     if (a.op != Op::Hash) {
-        for (const Chunk &ch : chunks) {
+        bool forked[kMaxSide] = {};
+        // Makes the caller's stream wait for every side stream used since
+        // the last join (also on the way out of an error).
+        auto join = [&]() {
+            hipError_t je = hipSuccess;
+            for (uint32_t k = 0; k < ctx->nside; ++k) {
+                if (!forked[k]) continue;
+                forked[k] = false;
+                hipError_t x = hipEventRecord(ctx->join_ev[k], ctx->side[k]);
+                if (x == hipSuccess) x = hipStreamWaitEvent(s, ctx->join_ev[k], 0);
+                if (je == hipSuccess) je = x;
+            }
+            return je;
+        };
+        auto fail = [&](hipError_t err) {
+            (void)join();
+            return map_err(err);
+        };
+        for (size_t ci = 0; ci < chunks.size(); ++ci) {
+            const Chunk &ch = chunks[ci];
+            hipStream_t ws = s;  // stream of this part's keygen and confusion
             if (uses_chain) {
                 e = timed(ctx, K_CHAIN, s, [&] {
-                    return launch_lhcs_chain(d_desc, d_runs + ch.run_begin, d_order, ch.run_end - ch.run_begin,
-                                             ctx->d_state, n, ctx->key.gamma, ctx->d_flags, s);
+                    return launch_lhcs_chain(d_runs + ch.run_begin, d_order, ch.run_end - ch.run_begin, ctx->d_state,
+                                             n, ctx->key.gamma, ctx->d_flags, s);
                 });
-                if (e != hipSuccess) return map_err(e);
-                e = timed(ctx, K_KEYGEN, s, [&] {
-                    return launch_lhcs_keygen(d_desc + ch.desc_begin, ch.desc_end - ch.desc_begin, n,
-                                              ctx->key.gamma, ctx->d_flags, s);
-                });
-                if (e != hipSuccess) return map_err(e);
+                if (e != hipSuccess) return fail(e);
             }
-            if (a.op == Op::DebugKeysched) continue;
-            for (const Group &g : ch.groups) {
-                tun.strip = pick_strip(ctx, dec_kernel, g.w, g.h);
-                e = timed(ctx, dec_kernel ? K_DEC : K_ENC, s, [&] {
-                    return launch_confuse(dec_kernel, d_desc, g.first, g.count, g.w, g.h, g.aligned, tun, s);
+            if (overlap) {
+                const uint32_t k = static_cast<uint32_t>(ci % ctx->nside);
+                ws = ctx->side[k];
+                e = hipEventRecord(ctx->fork_ev[k], s);
+                if (e == hipSuccess) e = hipStreamWaitEvent(ws, ctx->fork_ev[k], 0);
+                if (e != hipSuccess) return fail(e);
+                forked[k] = true;
+            }
+            if (uses_chain) {
+                e = timed(ctx, K_KEYGEN, ws, [&] {
+                    return launch_lhcs_keygen(d_desc + ch.desc_begin, ch.desc_end - ch.desc_begin, n,
+                                              ctx->key.gamma, ctx->d_flags, ws);
                 });
+                if (e != hipSuccess) return fail(e);
+            }
+            if (a.op != Op::DebugKeysched) {
+                for (const Group &g : ch.groups) {
+                    tun.strip = pick_strip(ctx, dec_kernel, g.w, g.h);
+                    e = timed(ctx, dec_kernel ? K_DEC : K_ENC, ws, [&] {
+                        return launch_confuse(dec_kernel, d_desc, g.first, g.count, g.w, g.h, g.aligned, tun, ws);
+                    });
+                    if (e != hipSuccess) return fail(e);
+                }
+            }
+            const bool span_ends = ci + 1 == chunks.size() || chunks[ci + 1].span != ch.span;
+            if (span_ends) {
+                e = join();
                 if (e != hipSuccess) return map_err(e);
             }
         }
@@ -443,6 +530,20 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
 extern "C" {
 
 uint32_t vc_protocol_version(void) { return 1; }
+
+int encrypt_frames_hashed(vc_cipher *ctx, size_t count, const uint8_t *const *frames, const vc_shape *shapes,
+                          const uint8_t *hashes, uint8_t *const *out, void *stream) {
+    if (count && (!frames || !shapes || !hashes || !out)) return VC_EINVAL;
+    CallArgs a{};
+    a.op = Op::EncryptHashed;
+    a.count = count;
+    a.in = frames;
+    a.shapes = shapes;
+    a.hashes = hashes;
+    a.out = out;
+    a.stream = static_cast<hipStream_t>(stream);
+    return locked_call(ctx, a);
+}
 
 const char *vc_strerror(int status) {
     switch (status) {
@@ -502,6 +603,11 @@ void cipher_destroy(vc_cipher *ctx) {
             if (ctx->h_stage[k]) (void)hipHostFree(ctx->h_stage[k]);
             if (ctx->d_stage[k]) (void)hipFree(ctx->d_stage[k]);
             if (ctx->stage_ev[k]) (void)hipEventDestroy(ctx->stage_ev[k]);
+        }
+        for (int k = 0; k < kMaxSide; ++k) {
+            if (ctx->side[k]) (void)hipStreamDestroy(ctx->side[k]);
+            if (ctx->fork_ev[k]) (void)hipEventDestroy(ctx->fork_ev[k]);
+            if (ctx->join_ev[k]) (void)hipEventDestroy(ctx->join_ev[k]);
         }
         if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
         if (ctx->d_state) (void)hipFree(ctx->d_state);
@@ -720,6 +826,14 @@ int vc_profile_reset(vc_cipher *ctx) {
         ctx->acc_n[k] = 0;
     }
     return map_err(e);
+}
+
+int vc_set_overlap(vc_cipher *ctx, uint32_t parts, uint32_t side_streams) {
+    if (!ctx || parts < 1 || parts > 64 || side_streams > kMaxSide) return VC_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->parts = parts;
+    ctx->nside = side_streams;
+    return VC_OK;
 }
 
 int vc_set_tuning(vc_cipher *ctx, uint32_t strip_width, uint32_t threads, int xcd_map) {

@@ -87,8 +87,14 @@ struct DecLayout {
     __host__ __device__ static uint32_t bytes(uint32_t h) { return dv_off(h) + 4 * 3 * (WT + 4); }
 };
 
-// Rows of the coalesced phase prefetched into registers per thread.
-constexpr uint32_t kPrefetchRows = 32;
+// Rows of the coalesced phase prefetched into registers per thread: as
+// many as keep the 1024-thread kernel within 96 VGPRs without spills, so
+// that a workgroup still fits on a CU beside one wave of the latency-bound
+// kernels (4 x 96 + 128 <= 512 VGPRs per SIMD).
+template <int WT>
+constexpr uint32_t prefetch_rows() {
+    return WT <= 16 ? 16 : 20;
+}
 
 // Funnel output of four consecutive strip columns k..k+3 of source row r,
 // channel c: the 40-bit little-endian run of pixels q..q+4 (mod w) shifted
@@ -119,9 +125,9 @@ __device__ __forceinline__ uint32_t window4_fast(const u32x4_a4 &v, uint32_t sh,
 // Encryption
 // ----------------------------------------------------------------------
 template <int WT, int NT>
-__global__ __launch_bounds__(NT) void confuse_xor_enc(const FrameDesc *__restrict__ desc, uint32_t first,
-                                                      uint32_t nframes, Geometry geo, uint32_t nstrips,
-                                                      int xcd_map, int aligned) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5, 8))) void confuse_xor_enc(
+    const FrameDesc *__restrict__ desc, uint32_t first, uint32_t nframes, Geometry geo, uint32_t nstrips, int xcd_map,
+    int aligned) {
     extern __shared__ __align__(16) uint8_t smem[];
     using Lay = EncLayout<WT>;
     constexpr uint32_t RS = Lay::RS;           // LDS row: channel c at c*WT + k
@@ -130,6 +136,7 @@ __global__ __launch_bounds__(NT) void confuse_xor_enc(const FrameDesc *__restric
     constexpr uint32_t LPG = KG / KPL;         // items per (row, channel)
     constexpr uint32_t GPR = 3 * WT / 4;       // dwords per full strip row
     constexpr uint32_t RP = NT / GPR;          // rows per pass of the coalesced phase
+    constexpr uint32_t kPrefetchRows = prefetch_rows<WT>();
 
     uint32_t fl, strip;
     map_workgroup(blockIdx.x, nstrips, xcd_map, fl, strip);
@@ -286,6 +293,7 @@ __global__ __launch_bounds__(NT) void confuse_xor_dec(const FrameDesc *__restric
     constexpr uint32_t RS = Lay::RS;
     constexpr uint32_t GPR = 3 * WT / 4;
     constexpr uint32_t RP = NT / GPR;
+    constexpr uint32_t kPrefetchRows = 32;  // C ^ B words in flight per thread
 
     uint32_t fl, strip;
     map_workgroup(blockIdx.x, nstrips, xcd_map, fl, strip);

@@ -29,13 +29,19 @@ struct FrameDesc {
     uint64_t L;          // 3wh
 };
 
-// One stream's frames inside a chunk, in sequence order: descriptor indices
-// order[first .. first+count).
+// One stream's frames inside a part, in sequence order: chain records
+// rec[first .. first+count).
 struct StreamRun {
     uint32_t slot;       // chain-state slot
     uint32_t first;
     uint32_t count;
     uint32_t pad;
+};
+
+// The chain's view of one frame, in sequence order within a run.
+struct ChainRec {
+    const uint8_t *hash;  // 32-byte frame hash H
+    double *IR;           // 2n x 4 LHCS_m iterates
 };
 
 enum KernelId { K_SHA = 0, K_CHAIN = 1, K_KEYGEN = 2, K_ENC = 3, K_DEC = 4, K_COUNT = 5 };
@@ -52,9 +58,8 @@ enum { FLAG_NONFINITE = 1 };
 // Launchers (each in the translation unit of its kernel).
 hipError_t launch_sha256_subframes(const FrameDesc *d_desc, uint32_t count, uint32_t n,
                                    hipStream_t s);
-hipError_t launch_lhcs_chain(const FrameDesc *d_desc, const StreamRun *d_runs,
-                             const uint32_t *d_order, uint32_t nruns, double *d_state,
-                             uint32_t n, double gamma, int *d_flags, hipStream_t s);
+hipError_t launch_lhcs_chain(const StreamRun *d_runs, const ChainRec *d_rec, uint32_t nruns,
+                             double *d_state, uint32_t n, double gamma, int *d_flags, hipStream_t s);
 hipError_t launch_lhcs_keygen(const FrameDesc *d_desc, uint32_t count, uint32_t n,
                               double gamma, int *d_flags, hipStream_t s);
 // Frames [first, first + count) of d_desc all have shape (w, h).

@@ -322,6 +322,7 @@ __global__ __launch_bounds__(128) void sha256_subframes_2w(const FrameDesc *__re
                                                            uint32_t n, uint32_t frames_per_group) {
     __shared__ __align__(16) uint32_t kwbuf[2][64][kKwStride];
     __shared__ uint32_t dig[64][9];
+    __builtin_amdgcn_s_setprio(2);  // latency-bound: ahead of the bandwidth-bound confusion waves
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t lf = lane / n, sub = lane % n;
     const uint32_t f = blockIdx.x * frames_per_group + lf;
@@ -406,6 +407,7 @@ __global__ __launch_bounds__(kShaMaxThreads) void sha256_subframes(const FrameDe
                                                                    uint32_t frames_per_group) {
     extern __shared__ uint32_t dig_raw[];  // blockDim.x x 9 words (9: no bank conflicts)
     uint32_t (*dig)[9] = reinterpret_cast<uint32_t (*)[9]>(dig_raw);
+    __builtin_amdgcn_s_setprio(2);
     const uint32_t tid = threadIdx.x;
     const uint32_t lf = tid / n, sub = tid % n;
     const uint32_t f = blockIdx.x * frames_per_group + lf;

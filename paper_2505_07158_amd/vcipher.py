@@ -56,6 +56,7 @@ def _load() -> C.CDLL:
     L.cipher_destroy.restype = None
     L.encrypt_frames.argtypes = [vp, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape), u8p, C.POINTER(vp), vp]
     L.decrypt_frames.argtypes = [vp, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape), u8p, C.POINTER(vp), vp]
+    L.encrypt_frames_hashed.argtypes = [vp, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape), u8p, C.POINTER(vp), vp]
     L.vc_hash_frames.argtypes = [vp, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape), u8p, vp]
     L.cipher_stream_reset.argtypes = [vp, C.c_uint32]
     L.cipher_stream_get_state.argtypes = [vp, C.c_uint32, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
@@ -65,13 +66,16 @@ def _load() -> C.CDLL:
     L.vc_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
     L.vc_profile_reset.argtypes = [vp]
     L.vc_set_tuning.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_int]
+    L.vc_set_overlap.argtypes = [vp, C.c_uint32, C.c_uint32]
     L.vc_debug_confuse.argtypes = [vp, C.c_int, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape),
                                    C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
     L.vc_debug_keysched.argtypes = [vp, C.c_size_t, C.POINTER(VcShape), u8p, C.POINTER(vp),
                                     C.POINTER(vp), C.POINTER(vp), vp]
-    for name in ("cipher_init", "encrypt_frames", "decrypt_frames", "vc_hash_frames", "cipher_stream_reset",
+    for name in ("cipher_init", "encrypt_frames", "encrypt_frames_hashed", "decrypt_frames", "vc_hash_frames",
+                 "cipher_stream_reset",
                  "cipher_stream_get_state", "cipher_stream_set_state", "cipher_status",
                  "vc_profile_enable", "vc_profile_read", "vc_profile_reset", "vc_set_tuning",
+                 "vc_set_overlap",
                  "vc_debug_confuse", "vc_debug_keysched", "vc_key_from_bytes"):
         getattr(L, name).restype = C.c_int
     return L
@@ -172,6 +176,18 @@ def encrypt_frames(ctx: int, frames: Sequence[torch.Tensor], streams: Sequence[i
     _check(rc, "encrypt_frames")
 
 
+def encrypt_frames_hashed(ctx: int, frames: Sequence[torch.Tensor], streams: Sequence[int], seqs: Sequence[int],
+                          hashes: torch.Tensor, out: Sequence[torch.Tensor],
+                          stream: Optional[torch.cuda.Stream] = None) -> None:
+    for t in list(frames) + list(out):
+        _check_frame(t)
+    if hashes.dtype != torch.uint8 or not hashes.is_cuda or hashes.numel() < 32 * len(frames):
+        raise ValueError("hashes must be a CUDA uint8 tensor of count*32 bytes")
+    rc = lib.encrypt_frames_hashed(C.c_void_p(ctx), len(frames), _ptrs(frames), _shapes(frames, streams, seqs),
+                                   C.c_void_p(hashes.data_ptr()), _ptrs(out), C.c_void_p(_stream_handle(stream)))
+    _check(rc, "encrypt_frames_hashed")
+
+
 def decrypt_frames(ctx: int, frames: Sequence[torch.Tensor], streams: Sequence[int], seqs: Sequence[int],
                    hashes: torch.Tensor, out: Sequence[torch.Tensor],
                    stream: Optional[torch.cuda.Stream] = None) -> None:
@@ -257,6 +273,10 @@ def vc_set_tuning(ctx: int, strip_width: int = 0, threads: int = 0, xcd_map: boo
     _check(lib.vc_set_tuning(C.c_void_p(ctx), strip_width, threads, 1 if xcd_map else 0), "vc_set_tuning")
 
 
+def vc_set_overlap(ctx: int, parts: int = 4, side_streams: int = 2) -> None:
+    _check(lib.vc_set_overlap(C.c_void_p(ctx), parts, side_streams), "vc_set_overlap")
+
+
 # --------------------------------------------------------------------------
 # convenience wrapper
 # --------------------------------------------------------------------------
@@ -320,6 +340,17 @@ class Cipher:
         self._advance(streams)
         return out, hashes
 
+    def encrypt_hashed(self, frames: FrameArg, hashes: torch.Tensor, streams: Optional[Sequence[int]] = None,
+                       out: Optional[FrameArg] = None, stream: Optional[torch.cuda.Stream] = None):
+        """Encrypt with frame hashes computed beforehand (see hash())."""
+        fr = _frames(frames)
+        streams = list(streams) if streams is not None else [0] * len(fr)
+        if out is None:
+            out = torch.empty_like(frames) if isinstance(frames, torch.Tensor) else [torch.empty_like(t) for t in fr]
+        encrypt_frames_hashed(self.ctx, fr, streams, self._seqs(streams), hashes, _frames(out), stream)
+        self._advance(streams)
+        return out
+
     def decrypt(self, frames: FrameArg, hashes: torch.Tensor, streams: Optional[Sequence[int]] = None,
                 out: Optional[FrameArg] = None, stream: Optional[torch.cuda.Stream] = None):
         fr = _frames(frames)
@@ -331,9 +362,10 @@ class Cipher:
         self._advance(streams)
         return out
 
-    def hash(self, frames: FrameArg, stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    def hash(self, frames: FrameArg, stream: Optional[torch.cuda.Stream] = None,
+             out: Optional[torch.Tensor] = None) -> torch.Tensor:
         fr = _frames(frames)
-        hashes = torch.empty((len(fr), 32), dtype=torch.uint8, device=fr[0].device)
+        hashes = out if out is not None else torch.empty((len(fr), 32), dtype=torch.uint8, device=fr[0].device)
         vc_hash_frames(self.ctx, fr, hashes, stream)
         return hashes
 
@@ -382,3 +414,6 @@ class Cipher:
 
     def tune(self, strip_width: int = 0, threads: int = 0, xcd_map: bool = True) -> None:
         vc_set_tuning(self.ctx, strip_width, threads, xcd_map)
+
+    def overlap(self, parts: int = 4, side_streams: int = 2) -> None:
+        vc_set_overlap(self.ctx, parts, side_streams)

@@ -154,6 +154,55 @@ def test_small_scratch_processes_in_chunks():
     small.close(); big.close()
 
 
+@pytest.mark.parametrize("parts,side", [(1, 0), (4, 2), (3, 1), (7, 4), (64, 3), (2, 0), (8, 8)])
+def test_overlap_settings_match_oracle(parts, side):
+    """Cutting a call into parts whose keygen and confusion run on side
+    streams never changes bytes: 13 frames of one stream against the
+    oracle, two streams interleaved in one call, and a scratch that holds
+    only three frames (spans of parts, scratch reused between spans)."""
+    dev = require_gpu()
+    kb = key_bytes(12)
+    n = 6
+    video = SynthVideo(96, 64, seed=12).frames(13)
+    Cs, Hs, _ = oracle_stream(kb, -1.0, n, list(video))
+    for scratch in (0, 3 * (96 * 64 * 3 + 1024) + 4096):
+        c = V().Cipher.from_bytes(kb, -1.0, n, scratch_bytes=scratch)
+        c.overlap(parts, side)
+        C, H = c.encrypt(to_dev(video, dev))
+        Cn, Hn = to_np(C), to_np(H)
+        for t in range(len(video)):
+            assert Hn[t].tobytes() == Hs[t], (scratch, t)
+            assert np.array_equal(Cn[t], Cs[t]), (scratch, t)
+        d = V().Cipher.from_bytes(kb, -1.0, n, scratch_bytes=scratch)
+        d.overlap(parts, side)
+        assert torch.equal(d.decrypt(C, H), to_dev(video, dev))
+        assert c.status() == 0 and d.status() == 0
+        c.close(); d.close()
+    # two streams interleaved in one call
+    other = SynthVideo(96, 64, seed=13).frames(5)
+    Co, Ho, _ = oracle_stream(kb, -1.0, n, list(other))
+    m = V().Cipher.from_bytes(kb, -1.0, n, max_streams=2)
+    m.overlap(parts, side)
+    frames = [video[0], other[0], video[1], other[1], other[2], video[2]]
+    streams = [0, 1, 0, 1, 1, 0]
+    seqs = [0, 0, 1, 1, 2, 2]
+    C, H = m.encrypt(torch.stack([to_dev(f, dev) for f in frames]), streams=streams)
+    Cn = to_np(C)
+    for k, (st, sq) in enumerate(zip(streams, seqs)):
+        ref = Cs[sq] if st == 0 else Co[sq]
+        assert np.array_equal(Cn[k], ref), k
+    m.close()
+
+
+def test_overlap_rejects_bad_arguments():
+    require_gpu()
+    c = V().Cipher.from_bytes(key_bytes(1), -1.0, 4)
+    for parts, side in [(0, 2), (65, 2), (4, 9)]:
+        with pytest.raises(V().VcError):
+            c.overlap(parts, side)
+    c.close()
+
+
 def test_state_export_import_resumes_stream():
     dev = require_gpu()
     kb = key_bytes(5)
@@ -203,3 +252,63 @@ def test_documented_errors():
     Vm.encrypt_frames(c.ctx, [f], [0], [0], H, [out])
     assert c.status() == 0
     c.close(); tiny.close()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("w,h,n,frames", [(3840, 2160, 32, 2), (1920, 1080, 256, 2), (1280, 720, 6, 3),
+                                          (720, 480, 32, 2), (1924, 1084, 32, 2)])
+def test_large_shapes_parity(w, h, n, frames):
+    """Largest frame of the serving mix (3840x2160), the second worker
+    count of the benchmark plan (n = 256), the paper's monitoring setting
+    (n = 6), SD, and a frame whose width is not a multiple of the strip."""
+    dev = require_gpu()
+    kb = key_bytes(7)
+    video = SynthVideo(w, h, seed=w + h + n).frames(frames)
+    c = V().Cipher.from_bytes(kb, -1.0, n)
+    C, H = c.encrypt(to_dev(video, dev))
+    Cs, Hs, _ = oracle_stream(kb, -1.0, n, list(video))
+    Cn, Hn = to_np(C), to_np(H)
+    for t in range(frames):
+        assert Hn[t].tobytes() == Hs[t], t
+        assert np.array_equal(Cn[t], Cs[t]), t
+    d = V().Cipher.from_bytes(kb, -1.0, n)
+    assert torch.equal(d.decrypt(C, H), to_dev(video, dev))
+    c.close(); d.close()
+
+
+def test_batch_shapes_xcd_split_and_ragged():
+    """Batches whose frame count is not a multiple of the 8 XCDs, frames of
+    two shapes in one call, and a ragged last strip (w = 100), checked
+    against the oracle confusion with oracle-generated D and B."""
+    dev = require_gpu()
+    rng = np.random.default_rng(99)
+    c = V().Cipher.from_bytes(key_bytes(8), -1.0, 4)
+    for shapes in ([(48, 100)] * 3, [(64, 64)] * 9 + [(33, 100)] * 2, [(120, 160)] * 17):
+        Ps = [rng.integers(0, 256, (h, w, 3), dtype=np.uint8) for h, w in shapes]
+        Ds = [rng.integers(0, 65536, 3 * h + 3 * w, dtype=np.uint16) for h, w in shapes]
+        Bs = [rng.integers(0, 256, (h, w, 3), dtype=np.uint8) for h, w in shapes]
+        outs = c.confuse([to_dev(p, dev) for p in Ps], [to_dev(x, dev) for x in Ds], [to_dev(x, dev) for x in Bs])
+        for P, D, B, o in zip(Ps, Ds, Bs, outs):
+            ref = oracle.confuse_enc(P, D, B)
+            assert np.array_equal(to_np(o), ref)
+        back = c.confuse(outs, [to_dev(x, dev) for x in Ds], [to_dev(x, dev) for x in Bs], decrypt=True)
+        for P, b in zip(Ps, back):
+            assert np.array_equal(to_np(b), P)
+    c.close()
+
+
+def test_encrypt_with_precomputed_hashes_matches():
+    dev = require_gpu()
+    kb = key_bytes(9)
+    frames = to_dev(SynthVideo(96, 64, seed=9).frames(5), dev)
+    a = V().Cipher.from_bytes(kb, -1.0, 6)
+    b = V().Cipher.from_bytes(kb, -1.0, 6)
+    Ca, Ha = a.encrypt(frames)
+    hs = torch.cuda.Stream()
+    H = b.hash(frames, stream=hs)
+    ev = torch.cuda.Event()
+    ev.record(hs)
+    torch.cuda.current_stream().wait_event(ev)
+    Cb = b.encrypt_hashed(frames, H)
+    assert torch.equal(H, Ha) and torch.equal(Cb, Ca)
+    a.close(); b.close()
