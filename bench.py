@@ -48,11 +48,13 @@ def parse():
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--strip", type=int, default=0, help="confusion strip width (0 = automatic)")
     ap.add_argument("--threads", type=int, default=0, help="confusion workgroup size (0 = automatic)")
-    ap.add_argument("--parts", type=int, default=4, help="sub-batches per call whose keygen and confusion "
+    ap.add_argument("--parts", type=int, default=3, help="sub-batches per call whose keygen and confusion "
                     "overlap the chain (1 = none)")
-    ap.add_argument("--side", type=int, default=2, help="side streams per context for that overlap")
-    ap.add_argument("--hw-queues", type=int, default=0,
-                    help="GPU_MAX_HW_QUEUES for this process (0 = HIP's default); must be set before HIP starts")
+    ap.add_argument("--side", type=int, default=3, help="side streams per context for that overlap")
+    ap.add_argument("--slots", type=int, default=2, help="scratch slots per context (one batch each)")
+    ap.add_argument("--hw-queues", type=int, default=16,
+                    help="GPU_MAX_HW_QUEUES for this process (0 = HIP's default of 4): the benchmark runs 5 streams "
+                    "of its own and 4 per context, and streams sharing a hardware queue are serialised")
     ap.add_argument("--latency-iters", type=int, default=30)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -62,19 +64,29 @@ def parse():
     return ap.parse_args()
 
 
-def measured_traffic(frames: int, w: int, h: int) -> dict:
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "confuse_xor_hbm_traffic_1080p_n32.txt")
+
+
+def measured_traffic(frames_per_launch: float, w: int, h: int) -> dict:
     """HBM bytes per launch of the confusion kernels from the committed
-    rocprofv3 counter runs (profiles/traffic.json), scaled by the copy
-    kernel's calibration.  Used only while the kernel source is the one the
-    counters were taken on, and for the same workload."""
+    rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE), scaled by what the
+    same counters read for a plain copy of known size.  The summary file
+    carries one JSON line with those figures; they are used only while the
+    kernel source is the one the counters were taken on and for the same
+    frames per launch."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "traffic.json")
     src = os.path.join(ROOT, "paper_2505_07158_amd", "csrc", "vc_confuse.hip")
-    if not os.path.exists(path):
+    if not os.path.exists(TRAFFIC_FILE):
         return {}
-    rec = json.load(open(path))
+    rec = None
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if line.startswith("{"):
+                rec = json.loads(line)
+    if rec is None:
+        return {}
     digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("source_sha256") != digest or rec.get("frames_per_launch") != frames or \
+    if rec.get("source_sha256") != digest or abs(rec.get("frames_per_launch", -1) - frames_per_launch) > 1e-9 or \
             rec.get("width") != w or rec.get("height") != h:
         return {}
     out = {}
@@ -82,7 +94,8 @@ def measured_traffic(frames: int, w: int, h: int) -> dict:
         fetch = k["fetch_kib"] * 1024 * rec["copy_scale_fetch"]
         write = k["write_kib"] * 1024 * rec["copy_scale_write"]
         out[name] = {"bytes_per_launch": round(fetch + write), "fetch_bytes": round(fetch), "write_bytes": round(write),
-                     "algorithmic_bytes": 9 * w * h * frames, "source": "profiles/traffic.json"}
+                     "algorithmic_bytes": round(9 * w * h * frames_per_launch),
+                     "source": os.path.relpath(TRAFFIC_FILE, ROOT)}
     return out
 
 
@@ -121,25 +134,32 @@ def main():
     frames = torch.from_numpy(host).to(dev)
     # Three-stage stream pipeline (a sender that hashes frames as they come
     # and encrypts them as the key chain allows, and a receiver): batch k is
-    # hashed while batch k-1 is encrypted and batch k-2 decrypted.  Hash and
-    # ciphertext buffers rotate over three slots.
-    NB = 3
+    # hashed while batch k-1 is encrypted and batch k-2 decrypted.  Sender
+    # and receiver alternate between two streams each, so that the key
+    # chain of one batch runs while the previous batch's keygen and
+    # confusion finish (the library orders the chain and its scratch slots
+    # across streams).  Hash and ciphertext buffers rotate over four slots.
+    NB = 4
     hbuf = [torch.empty((T, 32), dtype=torch.uint8, device=dev) for _ in range(NB)]
     cbuf = [torch.empty_like(frames) for _ in range(NB)]
-    plain = torch.empty_like(frames)
-    s_hash, s_enc, s_dec = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    plain = [torch.empty_like(frames) for _ in range(2)]
+    s_hash = torch.cuda.Stream()
+    s_enc = [torch.cuda.Stream() for _ in range(2)]
+    s_dec = [torch.cuda.Stream() for _ in range(2)]
     hashed = [torch.cuda.Event() for _ in range(NB)]
     ready = [torch.cuda.Event() for _ in range(NB)]
     freed = [torch.cuda.Event() for _ in range(NB)]
     per_frame_scratch = L + 2 * (3 * w + 3 * h) + 64 * n + 3 * 256
-    scratch = max(per_frame_scratch * T + (64 << 20), 256 << 20)
+    batch_scratch = per_frame_scratch * T + (64 << 20)
 
     def make_cipher(nn, scratch_bytes):
-        c = V.Cipher.from_bytes(kb, gamma, nn, scratch_bytes=scratch_bytes)
+        c = V.Cipher.from_bytes(kb, gamma, nn, scratch_bytes=scratch_bytes * args.slots)
         if args.strip or args.threads:
             c.tune(args.strip, args.threads)
-        c.overlap(args.parts, args.side)
+        c.overlap(args.parts, args.side, args.slots)
         return c
+
+    scratch = batch_scratch
 
     enc = make_cipher(n, scratch)
     dec = make_cipher(n, scratch)
@@ -151,16 +171,16 @@ def main():
         hashed[b].record(s_hash)
 
     def stage_enc(k):
-        b = k % NB
-        s_enc.wait_event(hashed[b])
-        enc.encrypt_hashed(frames, hbuf[b], out=cbuf[b], stream=s_enc)
-        ready[b].record(s_enc)
+        b, st = k % NB, s_enc[k % 2]
+        st.wait_event(hashed[b])
+        enc.encrypt_hashed(frames, hbuf[b], out=cbuf[b], stream=st)
+        ready[b].record(st)
 
     def stage_dec(k):
-        b = k % NB
-        s_dec.wait_event(ready[b])
-        dec.decrypt(cbuf[b], hbuf[b], out=plain, stream=s_dec)
-        freed[b].record(s_dec)
+        b, st = k % NB, s_dec[k % 2]
+        st.wait_event(ready[b])
+        dec.decrypt(cbuf[b], hbuf[b], out=plain[k % 2], stream=st)
+        freed[b].record(st)
 
     # Reference copy of known size (the plain-copy calibration of the HBM
     # byte counters when this benchmark runs under rocprofv3 --pmc).
@@ -173,7 +193,7 @@ def main():
     stage_enc(0)
     stage_dec(0)
     torch.cuda.synchronize()
-    roundtrip_ok = bool(torch.equal(plain, frames))
+    roundtrip_ok = bool(torch.equal(plain[0], frames))
     sample_frames = 4
     first_c = cbuf[0][:sample_frames].cpu().numpy()
     first_h = hbuf[0].cpu().numpy()
@@ -197,10 +217,10 @@ def main():
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    evs[0].record(s_dec)
+    evs[0].record(s_dec[(k - 3) % 2])
     for i in range(args.steps):
         stage_hash(k); stage_enc(k - 1); stage_dec(k - 2)
-        evs[i + 1].record(s_dec)
+        evs[i + 1].record(s_dec[(k - 2) % 2])
         k += 1
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -212,7 +232,7 @@ def main():
     # drain
     stage_enc(k - 1); stage_dec(k - 2); stage_dec(k - 1)
     torch.cuda.synchronize()
-    roundtrip_ok = roundtrip_ok and bool(torch.equal(plain, frames))
+    roundtrip_ok = roundtrip_ok and bool(torch.equal(plain[0], frames)) and bool(torch.equal(plain[1], frames))
     assert enc.status() == 0 and dec.status() == 0
 
     # ---- reference: the same work without the pipeline (encrypt_frames,
@@ -224,12 +244,12 @@ def main():
 
         def plain_step(j):
             b = j % 2
-            s_enc.wait_event(freed[b])
-            e3.encrypt(frames, out=cbuf[b], hashes=hbuf[b], stream=s_enc)
-            ready[b].record(s_enc)
-            s_dec.wait_event(ready[b])
-            d3.decrypt(cbuf[b], hbuf[b], out=plain, stream=s_dec)
-            freed[b].record(s_dec)
+            s_enc[0].wait_event(freed[b])
+            e3.encrypt(frames, out=cbuf[b], hashes=hbuf[b], stream=s_enc[0])
+            ready[b].record(s_enc[0])
+            s_dec[0].wait_event(ready[b])
+            d3.decrypt(cbuf[b], hbuf[b], out=plain[0], stream=s_dec[0])
+            freed[b].record(s_dec[0])
 
         torch.cuda.synchronize()
         plain_step(0)
@@ -241,8 +261,8 @@ def main():
         el3 = time.perf_counter() - a
         unpiped = {"value": round(T * args.unpipelined_steps / el3, 1), "unit": "frames/s",
                    "ms_per_step": round(1000 * el3 / args.unpipelined_steps, 3),
-                   "steps": args.unpipelined_steps, "roundtrip_ok": bool(torch.equal(plain, frames)),
-                   "mode": "encrypt_frames then decrypt_frames, sender and receiver streams"}
+                   "steps": args.unpipelined_steps, "roundtrip_ok": bool(torch.equal(plain[0], frames)),
+                   "mode": "encrypt_frames then decrypt_frames, one sender and one receiver stream"}
         e3.close()
         d3.close()
 
@@ -271,9 +291,8 @@ def main():
 
     roof_enc = hbm_roof("confuse_xor_enc")
     roof_dec = hbm_roof("confuse_xor_dec")
-    traffic = measured_traffic(T, w, h)
     for roof in (roof_enc, roof_dec):
-        t = traffic.get(roof["kernel"])
+        t = measured_traffic(roof["frames_per_launch"], w, h).get(roof["kernel"])
         if t is not None:
             roof["traffic"] = t["bytes_per_launch"]
             roof["traffic_detail"] = t
@@ -305,17 +324,18 @@ def main():
             s_hash.wait_event(freed[b])
             e2.hash(frames, stream=s_hash, out=hbuf[b])
             hashed[b].record(s_hash)
-            s_enc.wait_event(hashed[b])
-            e2.encrypt_hashed(frames, hbuf[b], out=cbuf[b], stream=s_enc)
-            ready[b].record(s_enc)
-            s_dec.wait_event(ready[b])
-            d2.decrypt(cbuf[b], hbuf[b], out=plain, stream=s_dec)
-            freed[b].record(s_dec)
+            se, sd = s_enc[k % 2], s_dec[k % 2]
+            se.wait_event(hashed[b])
+            e2.encrypt_hashed(frames, hbuf[b], out=cbuf[b], stream=se)
+            ready[b].record(se)
+            sd.wait_event(ready[b])
+            d2.decrypt(cbuf[b], hbuf[b], out=plain[k % 2], stream=sd)
+            freed[b].record(sd)
 
         torch.cuda.synchronize()
         step2(0)
         torch.cuda.synchronize()
-        ok2 = bool(torch.equal(plain, frames))
+        ok2 = bool(torch.equal(plain[0], frames))
         a = time.perf_counter()
         for k in range(args.second_steps):
             step2(k + 1)

@@ -30,8 +30,9 @@
  *    before anything is enqueued, so a call that fails enqueues nothing and
  *    leaves the chain states untouched.
  *  - Calls on one context are serialised internally (a mutex); chain-state
- *    updates happen in call order.  Work of one context must stay on one
- *    stream, or the caller orders the streams.
+ *    updates and scratch reuse are ordered by the library in call order, so
+ *    consecutive calls may use different streams.  Inputs must be ready on
+ *    the stream a call is given (the caller orders its own producers).
  *  - Protocol readings where the paper is silent (integrator, step, byte
  *    order, partitions, layouts) are frozen as protocol version 1; see
  *    vc_protocol_version.
@@ -169,18 +170,24 @@ int vc_profile_read(vc_cipher *ctx, int kernel_id, double *total_ms, uint64_t *l
 int vc_profile_reset(vc_cipher *ctx);
 const char *vc_kernel_name(int kernel_id);
 
-/* Overlap of the LHCS_m chain with keygen and confusion inside one call.
- * Frames of a call are cut into `parts` sub-batches in call order (1 = no
- * cut, at most 64); the chain of every part runs on the caller's stream,
- * the keygen and confusion of part k on side stream k mod side_streams of
- * the context (0 = everything on the caller's stream, at most 8), and the
- * caller's stream waits for the side streams before the call's work is
- * complete.  Defaults: 4 parts, 2 side streams.  A process whose streams
- * outnumber the device's hardware queues (GPU_MAX_HW_QUEUES, 4 by default
- * in HIP) shares queues between streams, which serialises their work; size
- * the queue count to the streams in use.  Never changes output bytes.
- * VC_EINVAL for out-of-range arguments. */
-int vc_set_overlap(vc_cipher *ctx, uint32_t parts, uint32_t side_streams);
+/* Overlap of the LHCS_m chain with keygen and confusion.  Every chain step
+ * of a context runs on one context-owned stream, in call order, after the
+ * caller's stream has reached the call.  The scratch is split into
+ * `scratch_slots` equal slots (1..4); each span of frames whose IR, D and B
+ * fit a slot takes the next slot once its previous user is done.  Each span
+ * is cut into `parts` sub-batches in call order (1..64); keygen and
+ * confusion of part k run on side stream k mod side_streams (0..8; 0 = on
+ * the chain stream), after the chain of part k.  The caller's stream waits
+ * for the call's side work before its later work, so results are
+ * stream-ordered as usual; a caller that issues consecutive calls on
+ * different streams lets the chain of one call overlap the keygen and
+ * confusion of the previous one.  Defaults: 3 parts, 3 side streams,
+ * 2 slots.  A process whose streams outnumber the device's hardware queues
+ * (GPU_MAX_HW_QUEUES, 4 by default in HIP) shares queues between streams,
+ * which serialises their work; size the queue count to the streams in use.
+ * Changing the slot count waits for the device.  Never changes output
+ * bytes.  VC_EINVAL for out-of-range arguments. */
+int vc_set_overlap(vc_cipher *ctx, uint32_t parts, uint32_t side_streams, uint32_t scratch_slots);
 
 /* Strip width (pixels: 4, 8, 16, 32 or 64; 0 = automatic) and
  * threads per workgroup (256, 512 or 1024; 0 = automatic) of the

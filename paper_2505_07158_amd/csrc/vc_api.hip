@@ -10,12 +10,20 @@
 //   decrypt: per part: lhcs_chain -> lhcs_keygen -> confuse_xor_dec
 // The chain is the serial spine of a stream (frame t+1 starts from the end
 // of frame t), while the keygen and confusion of a frame need only that
-// frame's IR.  So each scratch span is cut into parts in call order: the
-// chain of every part runs on the caller's stream, and the keygen and
-// confusion of part k run on one of the context's side streams, forked
-// after the chain of part k; keygen k then overlaps the chain of part k+1.
-// The caller's stream joins the side streams at the end of every span, so
-// the call is stream-ordered as a whole and scratch is never reused early.
+// frame's IR.  So:
+//  - every chain launch of the context runs on one context-owned chain
+//    stream, in call order, after an event recorded on the caller's stream
+//    at call entry (the call's inputs are ready);
+//  - the scratch is divided into slots; each span of frames whose IR, D and
+//    B fit a slot takes the next slot, and its first chain waits until the
+//    slot's previous user has finished with it;
+//  - each span is cut into parts in call order; keygen and confusion of
+//    part k run on side stream k mod s, forked after the chain of part k,
+//    so keygen k overlaps the chain of part k+1;
+//  - the caller's stream waits for the side streams before the call ends,
+//    so the call is stream-ordered as a whole.
+// A caller that issues consecutive calls on different streams therefore
+// lets the chain of call k+1 start while call k's keygen and confusion run.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -39,6 +47,7 @@ constexpr double kGammaHi = -0.06;
 constexpr uint32_t kMaxDim = 65535;
 constexpr int kRing = 4;
 constexpr int kMaxSide = 8;
+constexpr int kMaxSlots = 4;
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
@@ -100,13 +109,21 @@ struct vc_cipher {
     // tuning
     uint32_t strip = 0, threads = 0;
     int xcd_map = 1;
-    // overlap of the chain with keygen + confusion (side streams at default
+    // overlap of the chain with keygen + confusion (streams at default
     // priority, created on first use so that idle contexts hold none)
-    uint32_t parts = 4;
-    uint32_t nside = 2;
+    uint32_t parts = 3;
+    uint32_t nside = 3;
+    uint32_t nslots = 2;
+    uint32_t slot_next = 0;
+    hipStream_t chain_stream = nullptr;
+    hipEvent_t in_ev = nullptr;
     hipStream_t side[kMaxSide] = {};
     hipEvent_t fork_ev[kMaxSide] = {};
     hipEvent_t join_ev[kMaxSide] = {};
+    // per scratch slot: events recorded on the worker streams that last used
+    // it (index k = side stream k, or the chain stream when there is none)
+    hipEvent_t slot_ev[kMaxSlots][kMaxSide] = {};
+    bool slot_live[kMaxSlots][kMaxSide] = {};
     // profiling
     bool profile = false;
     std::vector<PendingEvent> pending;
@@ -255,16 +272,24 @@ struct CallArgs {
     hipStream_t stream;
 };
 
-hipError_t ensure_side(vc_cipher *ctx, uint32_t count) {
-    for (uint32_t k = 0; k < count; ++k) {
-        if (ctx->side[k]) continue;
-        hipError_t e = hipEventCreateWithFlags(&ctx->fork_ev[k], hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join_ev[k], hipEventDisableTiming);
-        if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking);
-        if (e != hipSuccess) return e;
+hipError_t ensure_streams(vc_cipher *ctx) {
+    hipError_t e = hipSuccess;
+    if (!ctx->chain_stream) {
+        e = hipEventCreateWithFlags(&ctx->in_ev, hipEventDisableTiming);
+        for (int k = 0; k < kMaxSide && e == hipSuccess; ++k) {
+            e = hipEventCreateWithFlags(&ctx->fork_ev[k], hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->join_ev[k], hipEventDisableTiming);
+            for (int q = 0; q < kMaxSlots && e == hipSuccess; ++q)
+                e = hipEventCreateWithFlags(&ctx->slot_ev[q][k], hipEventDisableTiming);
+        }
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&ctx->chain_stream, hipStreamNonBlocking);
     }
-    return hipSuccess;
+    for (uint32_t k = 0; k < ctx->nside && e == hipSuccess; ++k)
+        if (!ctx->side[k]) e = hipStreamCreateWithFlags(&ctx->side[k], hipStreamNonBlocking);
+    return e;
 }
+
+size_t slot_bytes(const vc_cipher *ctx) { return ctx->scratch_bytes / ctx->nslots / 256 * 256; }
 
 int run_call(vc_cipher *ctx, const CallArgs &a) {
     const bool encrypting = a.op == Op::Encrypt || a.op == Op::EncryptHashed;
@@ -287,7 +312,7 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
             return VC_EINVAL;
         if (a.op == Op::DebugConfuse && (!a.dbgD[f] || !a.dbgB[f])) return VC_EINVAL;
         if (a.op == Op::DebugKeysched && (!a.kIR[f] || !a.kD[f] || !a.kB[f])) return VC_EINVAL;
-        if (uses_scratch && scratch_need(s, n) > ctx->scratch_bytes) return VC_ENOMEM;
+        if (uses_scratch && scratch_need(s, n) > slot_bytes(ctx)) return VC_ENOMEM;
         if (uses_chain) {
             if (s.stream >= ctx->max_streams) return VC_EINVAL;
             auto it = seq_next.find(s.stream);
@@ -297,13 +322,14 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         }
     }
     if (count == 0) return VC_OK;
-    if ((encrypting || a.op == Op::Decrypt) && ctx->nside > 0 && ctx->parts > 1) {
-        const hipError_t e = ensure_side(ctx, ctx->nside);
+    if (uses_chain) {
+        const hipError_t e = ensure_streams(ctx);
         if (e != hipSuccess) return map_err(e);
     }
 
-    // ---- plan spans (consecutive frames whose scratch fits) and parts ----
-    const bool overlap = (encrypting || a.op == Op::Decrypt) && ctx->nside > 0 && ctx->parts > 1;
+    // ---- plan spans (consecutive frames whose scratch fits a slot) and parts ----
+    const bool overlap = (encrypting || a.op == Op::Decrypt) && ctx->parts > 1;
+    const size_t cap = slot_bytes(ctx);
     struct Part {
         size_t b, e;
         uint32_t span;
@@ -315,7 +341,7 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         uint64_t used = 0;
         for (size_t f = 0; f < count; ++f) {
             const uint64_t need = uses_scratch ? scratch_need(a.shapes[f], n) : 0;
-            if (f > b && used + need > ctx->scratch_bytes) {
+            if (f > b && used + need > cap) {
                 spans.push_back({b, f});
                 b = f;
                 used = 0;
@@ -337,11 +363,14 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
     std::vector<ChainRec> order;
     std::vector<Chunk> chunks;
     std::vector<uint32_t> desc_of(count);
+    // span j of this call uses scratch slot (slot_next + j) mod nslots
+    const uint32_t nspans = parts.empty() ? 0 : parts.back().span + 1;
+    auto slot_of = [&](uint32_t span) { return (ctx->slot_next + span) % ctx->nslots; };
     uint64_t off = 0;
     for (size_t pi = 0; pi < parts.size(); ++pi) {
         const Part &pt = parts[pi];
         const std::pair<size_t, size_t> sp{pt.b, pt.e};
-        if (pi > 0 && parts[pi - 1].span != pt.span) off = 0;  // a new span reuses the scratch
+        if (pi == 0 || parts[pi - 1].span != pt.span) off = slot_of(pt.span) * cap;
         Chunk ch;
         ch.span = pt.span;
         ch.desc_begin = static_cast<uint32_t>(sp.first);
@@ -458,50 +487,82 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         e = timed(ctx, K_SHA, s, [&] { return launch_sha256_subframes(d_desc, static_cast<uint32_t>(count), n, s); });
         if (e != hipSuccess) return map_err(e);
     }
-    if (a.op != Op::Hash) {
-        bool forked[kMaxSide] = {};
-        // Makes the caller's stream wait for every side stream used since
-        // the last join (also on the way out of an error).
+    if (uses_chain) {
+        hipStream_t cs = ctx->chain_stream;
+        // worker streams for keygen + confusion: the side streams, or the
+        // chain stream itself when there are none
+        const uint32_t nw = ctx->nside ? ctx->nside : 1;
+        auto wstream = [&](uint32_t k) { return ctx->nside ? ctx->side[k] : cs; };
+        bool used_call[kMaxSide] = {}, used_span[kMaxSide] = {};
+        auto release_span = [&](uint32_t span) {
+            hipError_t re = hipSuccess;
+            const uint32_t q = slot_of(span);
+            for (uint32_t k = 0; k < nw; ++k) {
+                if (!used_span[k]) continue;
+                used_span[k] = false;
+                const hipError_t x = hipEventRecord(ctx->slot_ev[q][k], wstream(k));
+                if (x == hipSuccess) ctx->slot_live[q][k] = true;
+                if (re == hipSuccess) re = x;
+            }
+            return re;
+        };
+        // Makes the caller's stream wait for every worker stream of the call.
         auto join = [&]() {
             hipError_t je = hipSuccess;
-            for (uint32_t k = 0; k < ctx->nside; ++k) {
-                if (!forked[k]) continue;
-                forked[k] = false;
-                hipError_t x = hipEventRecord(ctx->join_ev[k], ctx->side[k]);
+            for (uint32_t k = 0; k < nw; ++k) {
+                if (!used_call[k]) continue;
+                used_call[k] = false;
+                hipError_t x = hipEventRecord(ctx->join_ev[k], wstream(k));
                 if (x == hipSuccess) x = hipStreamWaitEvent(s, ctx->join_ev[k], 0);
                 if (je == hipSuccess) je = x;
             }
             return je;
         };
+        int cur_span = -1;
         auto fail = [&](hipError_t err) {
+            if (cur_span >= 0 && uses_scratch) (void)release_span(static_cast<uint32_t>(cur_span));
             (void)join();
             return map_err(err);
         };
+        e = hipEventRecord(ctx->in_ev, s);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, ctx->in_ev, 0);
+        if (e != hipSuccess) return map_err(e);
         for (size_t ci = 0; ci < chunks.size(); ++ci) {
             const Chunk &ch = chunks[ci];
-            hipStream_t ws = s;  // stream of this part's keygen and confusion
-            if (uses_chain) {
-                e = timed(ctx, K_CHAIN, s, [&] {
-                    return launch_lhcs_chain(d_runs + ch.run_begin, d_order, ch.run_end - ch.run_begin, ctx->d_state,
-                                             n, ctx->key.gamma, ctx->d_flags, s);
-                });
-                if (e != hipSuccess) return fail(e);
+            if (static_cast<int>(ch.span) != cur_span) {
+                if (cur_span >= 0 && uses_scratch) {
+                    e = release_span(static_cast<uint32_t>(cur_span));
+                    if (e != hipSuccess) return fail(e);
+                }
+                cur_span = static_cast<int>(ch.span);
+                if (uses_scratch) {  // wait until the slot's previous user is done with it
+                    const uint32_t q = slot_of(ch.span);
+                    for (int k = 0; k < kMaxSide; ++k) {
+                        if (!ctx->slot_live[q][k]) continue;
+                        e = hipStreamWaitEvent(cs, ctx->slot_ev[q][k], 0);
+                        if (e != hipSuccess) return fail(e);
+                        ctx->slot_live[q][k] = false;
+                    }
+                }
             }
-            if (overlap) {
-                const uint32_t k = static_cast<uint32_t>(ci % ctx->nside);
-                ws = ctx->side[k];
-                e = hipEventRecord(ctx->fork_ev[k], s);
+            e = timed(ctx, K_CHAIN, cs, [&] {
+                return launch_lhcs_chain(d_runs + ch.run_begin, d_order, ch.run_end - ch.run_begin, ctx->d_state, n,
+                                         ctx->key.gamma, ctx->d_flags, cs);
+            });
+            if (e != hipSuccess) return fail(e);
+            const uint32_t k = static_cast<uint32_t>(ci % nw);
+            hipStream_t ws = wstream(k);
+            if (ws != cs) {
+                e = hipEventRecord(ctx->fork_ev[k], cs);
                 if (e == hipSuccess) e = hipStreamWaitEvent(ws, ctx->fork_ev[k], 0);
                 if (e != hipSuccess) return fail(e);
-                forked[k] = true;
             }
-            if (uses_chain) {
-                e = timed(ctx, K_KEYGEN, ws, [&] {
-                    return launch_lhcs_keygen(d_desc + ch.desc_begin, ch.desc_end - ch.desc_begin, n,
-                                              ctx->key.gamma, ctx->d_flags, ws);
-                });
-                if (e != hipSuccess) return fail(e);
-            }
+            used_call[k] = used_span[k] = true;
+            e = timed(ctx, K_KEYGEN, ws, [&] {
+                return launch_lhcs_keygen(d_desc + ch.desc_begin, ch.desc_end - ch.desc_begin, n, ctx->key.gamma,
+                                          ctx->d_flags, ws);
+            });
+            if (e != hipSuccess) return fail(e);
             if (a.op != Op::DebugKeysched) {
                 for (const Group &g : ch.groups) {
                     tun.strip = pick_strip(ctx, dec_kernel, g.w, g.h);
@@ -511,9 +572,21 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
                     if (e != hipSuccess) return fail(e);
                 }
             }
-            const bool span_ends = ci + 1 == chunks.size() || chunks[ci + 1].span != ch.span;
-            if (span_ends) {
-                e = join();
+        }
+        if (cur_span >= 0 && uses_scratch) {
+            e = release_span(static_cast<uint32_t>(cur_span));
+            if (e != hipSuccess) return fail(e);
+        }
+        e = join();
+        if (e != hipSuccess) return map_err(e);
+        if (uses_scratch) ctx->slot_next = (ctx->slot_next + nspans) % ctx->nslots;
+    } else if (a.op == Op::DebugConfuse) {
+        for (const Chunk &ch : chunks) {
+            for (const Group &g : ch.groups) {
+                tun.strip = pick_strip(ctx, dec_kernel, g.w, g.h);
+                e = timed(ctx, dec_kernel ? K_DEC : K_ENC, s, [&] {
+                    return launch_confuse(dec_kernel, d_desc, g.first, g.count, g.w, g.h, g.aligned, tun, s);
+                });
                 if (e != hipSuccess) return map_err(e);
             }
         }
@@ -608,7 +681,11 @@ void cipher_destroy(vc_cipher *ctx) {
             if (ctx->side[k]) (void)hipStreamDestroy(ctx->side[k]);
             if (ctx->fork_ev[k]) (void)hipEventDestroy(ctx->fork_ev[k]);
             if (ctx->join_ev[k]) (void)hipEventDestroy(ctx->join_ev[k]);
+            for (int q = 0; q < kMaxSlots; ++q)
+                if (ctx->slot_ev[q][k]) (void)hipEventDestroy(ctx->slot_ev[q][k]);
         }
+        if (ctx->chain_stream) (void)hipStreamDestroy(ctx->chain_stream);
+        if (ctx->in_ev) (void)hipEventDestroy(ctx->in_ev);
         if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
         if (ctx->d_state) (void)hipFree(ctx->d_state);
         if (ctx->d_flags) (void)hipFree(ctx->d_flags);
@@ -828,9 +905,21 @@ int vc_profile_reset(vc_cipher *ctx) {
     return map_err(e);
 }
 
-int vc_set_overlap(vc_cipher *ctx, uint32_t parts, uint32_t side_streams) {
-    if (!ctx || parts < 1 || parts > 64 || side_streams > kMaxSide) return VC_EINVAL;
+int vc_set_overlap(vc_cipher *ctx, uint32_t parts, uint32_t side_streams, uint32_t scratch_slots) {
+    if (!ctx || parts < 1 || parts > 64 || side_streams > kMaxSide || scratch_slots < 1 || scratch_slots > kMaxSlots)
+        return VC_EINVAL;
     std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return VC_EDEVICE;
+    if (scratch_slots != ctx->nslots) {
+        // slot boundaries move: let all work that uses the scratch finish
+        const hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return map_err(e);
+        for (auto &row : ctx->slot_live)
+            for (bool &b : row) b = false;
+        ctx->nslots = scratch_slots;
+        ctx->slot_next = 0;
+    }
     ctx->parts = parts;
     ctx->nside = side_streams;
     return VC_OK;

@@ -66,7 +66,7 @@ def _load() -> C.CDLL:
     L.vc_profile_read.argtypes = [vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]
     L.vc_profile_reset.argtypes = [vp]
     L.vc_set_tuning.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_int]
-    L.vc_set_overlap.argtypes = [vp, C.c_uint32, C.c_uint32]
+    L.vc_set_overlap.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_uint32]
     L.vc_debug_confuse.argtypes = [vp, C.c_int, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape),
                                    C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
     L.vc_debug_keysched.argtypes = [vp, C.c_size_t, C.POINTER(VcShape), u8p, C.POINTER(vp),
@@ -273,8 +273,8 @@ def vc_set_tuning(ctx: int, strip_width: int = 0, threads: int = 0, xcd_map: boo
     _check(lib.vc_set_tuning(C.c_void_p(ctx), strip_width, threads, 1 if xcd_map else 0), "vc_set_tuning")
 
 
-def vc_set_overlap(ctx: int, parts: int = 4, side_streams: int = 2) -> None:
-    _check(lib.vc_set_overlap(C.c_void_p(ctx), parts, side_streams), "vc_set_overlap")
+def vc_set_overlap(ctx: int, parts: int = 3, side_streams: int = 3, scratch_slots: int = 2) -> None:
+    _check(lib.vc_set_overlap(C.c_void_p(ctx), parts, side_streams, scratch_slots), "vc_set_overlap")
 
 
 # --------------------------------------------------------------------------
@@ -415,5 +415,5 @@ class Cipher:
     def tune(self, strip_width: int = 0, threads: int = 0, xcd_map: bool = True) -> None:
         vc_set_tuning(self.ctx, strip_width, threads, xcd_map)
 
-    def overlap(self, parts: int = 4, side_streams: int = 2) -> None:
-        vc_set_overlap(self.ctx, parts, side_streams)
+    def overlap(self, parts: int = 3, side_streams: int = 3, scratch_slots: int = 2) -> None:
+        vc_set_overlap(self.ctx, parts, side_streams, scratch_slots)

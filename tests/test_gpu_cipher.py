@@ -154,35 +154,37 @@ def test_small_scratch_processes_in_chunks():
     small.close(); big.close()
 
 
-@pytest.mark.parametrize("parts,side", [(1, 0), (4, 2), (3, 1), (7, 4), (64, 3), (2, 0), (8, 8)])
-def test_overlap_settings_match_oracle(parts, side):
-    """Cutting a call into parts whose keygen and confusion run on side
-    streams never changes bytes: 13 frames of one stream against the
-    oracle, two streams interleaved in one call, and a scratch that holds
-    only three frames (spans of parts, scratch reused between spans)."""
+@pytest.mark.parametrize("parts,side,slots", [(1, 0, 1), (4, 2, 2), (3, 1, 3), (7, 4, 2), (64, 3, 4), (2, 0, 2),
+                                               (8, 8, 1)])
+def test_overlap_settings_match_oracle(parts, side, slots):
+    """Parts on side streams, chains on the context's chain stream and
+    scratch slots never change bytes: 13 frames of one stream against the
+    oracle (default scratch, and a scratch whose slots hold one or two frames,
+    so spans reuse slots inside one call), then two streams interleaved in
+    one call."""
     dev = require_gpu()
     kb = key_bytes(12)
     n = 6
     video = SynthVideo(96, 64, seed=12).frames(13)
     Cs, Hs, _ = oracle_stream(kb, -1.0, n, list(video))
-    for scratch in (0, 3 * (96 * 64 * 3 + 1024) + 4096):
+    per_frame = 18432 + 1024 + 512  # B, D and IR of one 96x64 frame at n = 6, 256-byte aligned
+    for scratch in (0, slots * (per_frame + per_frame // 2), slots * 2 * per_frame):
         c = V().Cipher.from_bytes(kb, -1.0, n, scratch_bytes=scratch)
-        c.overlap(parts, side)
+        c.overlap(parts, side, slots)
         C, H = c.encrypt(to_dev(video, dev))
         Cn, Hn = to_np(C), to_np(H)
         for t in range(len(video)):
             assert Hn[t].tobytes() == Hs[t], (scratch, t)
             assert np.array_equal(Cn[t], Cs[t]), (scratch, t)
         d = V().Cipher.from_bytes(kb, -1.0, n, scratch_bytes=scratch)
-        d.overlap(parts, side)
+        d.overlap(parts, side, slots)
         assert torch.equal(d.decrypt(C, H), to_dev(video, dev))
         assert c.status() == 0 and d.status() == 0
         c.close(); d.close()
-    # two streams interleaved in one call
     other = SynthVideo(96, 64, seed=13).frames(5)
     Co, Ho, _ = oracle_stream(kb, -1.0, n, list(other))
     m = V().Cipher.from_bytes(kb, -1.0, n, max_streams=2)
-    m.overlap(parts, side)
+    m.overlap(parts, side, slots)
     frames = [video[0], other[0], video[1], other[1], other[2], video[2]]
     streams = [0, 1, 0, 1, 1, 0]
     seqs = [0, 0, 1, 1, 2, 2]
@@ -194,12 +196,57 @@ def test_overlap_settings_match_oracle(parts, side):
     m.close()
 
 
+@pytest.mark.parametrize("slots", [1, 2, 3])
+def test_calls_on_alternating_streams_match_oracle(slots):
+    """Consecutive calls of one context on different caller streams: the
+    library orders the chain and the scratch reuse itself.  Batches of 3
+    frames alternate between two streams (with a scratch of one batch per
+    slot, so every call reuses a slot another stream's call wrote), then the
+    receiver decrypts on two other streams."""
+    dev = require_gpu()
+    kb = key_bytes(14)
+    n = 5
+    video = SynthVideo(80, 48, seed=14).frames(15)
+    Cs, Hs, _ = oracle_stream(kb, -1.0, n, list(video))
+    per = 3 * (80 * 48 * 3 + 256 + 2 * (3 * 80 + 3 * 48) + 256 + 64 * n + 256)
+    src = to_dev(video, dev)
+    enc = V().Cipher.from_bytes(kb, -1.0, n, scratch_bytes=per * slots)
+    dec = V().Cipher.from_bytes(kb, -1.0, n, scratch_bytes=per * slots)
+    enc.overlap(2, 2, slots)
+    dec.overlap(3, 1, slots)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    C = torch.empty_like(src)
+    H = torch.empty((len(video), 32), dtype=torch.uint8, device=dev)
+    Q = torch.empty_like(src)
+    torch.cuda.synchronize()
+    done = []
+    for k in range(5):
+        st = sa if k % 2 == 0 else sb
+        enc.encrypt(src[3 * k:3 * k + 3], out=C[3 * k:3 * k + 3], hashes=H[3 * k:3 * k + 3], stream=st)
+        ev = torch.cuda.Event()
+        ev.record(st)
+        done.append(ev)
+    da, db = torch.cuda.Stream(), torch.cuda.Stream()
+    for k in range(5):
+        st = da if k % 2 == 0 else db
+        st.wait_event(done[k])
+        dec.decrypt(C[3 * k:3 * k + 3], H[3 * k:3 * k + 3], out=Q[3 * k:3 * k + 3], stream=st)
+    torch.cuda.synchronize()
+    Cn, Hn = to_np(C), to_np(H)
+    for t in range(len(video)):
+        assert Hn[t].tobytes() == Hs[t], t
+        assert np.array_equal(Cn[t], Cs[t]), t
+    assert torch.equal(Q, src)
+    assert enc.status() == 0 and dec.status() == 0
+    enc.close(); dec.close()
+
+
 def test_overlap_rejects_bad_arguments():
     require_gpu()
     c = V().Cipher.from_bytes(key_bytes(1), -1.0, 4)
-    for parts, side in [(0, 2), (65, 2), (4, 9)]:
+    for parts, side, slots in [(0, 2, 2), (65, 2, 2), (4, 9, 2), (4, 2, 0), (4, 2, 5)]:
         with pytest.raises(V().VcError):
-            c.overlap(parts, side)
+            c.overlap(parts, side, slots)
     c.close()
 
 
