@@ -47,6 +47,7 @@ def parse():
     ap.add_argument("--width", type=int, default=1920)
     ap.add_argument("--height", type=int, default=1080)
     ap.add_argument("--strip", type=int, default=0, help="confusion strip width (0 = automatic)")
+    ap.add_argument("--passes", type=int, default=2, help="confusion passes: 2 (row + column) or 1 (fused)")
     ap.add_argument("--threads", type=int, default=0, help="confusion workgroup size (0 = automatic)")
     ap.add_argument("--parts", type=int, default=3, help="sub-batches per call whose keygen and confusion "
                     "overlap the chain (1 = none)")
@@ -64,7 +65,16 @@ def parse():
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "confuse_xor_hbm_traffic_1080p_n32.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "confusion_hbm_traffic_1080p_n32.txt")
+
+
+def confusion_source_digest() -> str:
+    """sha256 over the confusion kernels' sources (single- and two-pass)."""
+    import hashlib
+    hs = hashlib.sha256()
+    for f in ("vc_confuse.hip", "vc_shift.hip"):
+        hs.update(open(os.path.join(ROOT, "paper_2505_07158_amd", "csrc", f), "rb").read())
+    return hs.hexdigest()
 
 
 def measured_traffic(frames_per_launch: float, w: int, h: int) -> dict:
@@ -74,8 +84,6 @@ def measured_traffic(frames_per_launch: float, w: int, h: int) -> dict:
     carries one JSON line with those figures; they are used only while the
     kernel source is the one the counters were taken on and for the same
     frames per launch."""
-    import hashlib
-    src = os.path.join(ROOT, "paper_2505_07158_amd", "csrc", "vc_confuse.hip")
     if not os.path.exists(TRAFFIC_FILE):
         return {}
     rec = None
@@ -85,16 +93,16 @@ def measured_traffic(frames_per_launch: float, w: int, h: int) -> dict:
                 rec = json.loads(line)
     if rec is None:
         return {}
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("source_sha256") != digest or abs(rec.get("frames_per_launch", -1) - frames_per_launch) > 1e-9 or \
+    if rec.get("source_sha256") != confusion_source_digest() or abs(rec.get("frames_per_launch", -1) - frames_per_launch) > 1e-9 or \
             rec.get("width") != w or rec.get("height") != h:
         return {}
     out = {}
     for name, k in rec.get("kernels", {}).items():
         fetch = k["fetch_kib"] * 1024 * rec["copy_scale_fetch"]
         write = k["write_kib"] * 1024 * rec["copy_scale_write"]
+        per_px = 6 if name.startswith("row_shift") else 9
         out[name] = {"bytes_per_launch": round(fetch + write), "fetch_bytes": round(fetch), "write_bytes": round(write),
-                     "algorithmic_bytes": round(9 * w * h * frames_per_launch),
+                     "algorithmic_bytes": round(per_px * w * h * frames_per_launch),
                      "source": os.path.relpath(TRAFFIC_FILE, ROOT)}
     return out
 
@@ -149,7 +157,7 @@ def main():
     hashed = [torch.cuda.Event() for _ in range(NB)]
     ready = [torch.cuda.Event() for _ in range(NB)]
     freed = [torch.cuda.Event() for _ in range(NB)]
-    per_frame_scratch = L + 2 * (3 * w + 3 * h) + 64 * n + 3 * 256
+    per_frame_scratch = V.vc_scratch_per_frame(w, h, n)
     batch_scratch = per_frame_scratch * T + (64 << 20)
 
     def make_cipher(nn, scratch_bytes):
@@ -157,12 +165,17 @@ def main():
         if args.strip or args.threads:
             c.tune(args.strip, args.threads)
         c.overlap(args.parts, args.side, args.slots)
+        c.passes(args.passes)
         return c
 
     scratch = batch_scratch
 
     enc = make_cipher(n, scratch)
     dec = make_cipher(n, scratch)
+    # Launch counting from the start, so that a profiler's dispatch list can
+    # be matched to the timed region (dispatch_window in the output).
+    enc.profile(True)
+    dec.profile(True)
 
     def stage_hash(k):
         b = k % NB
@@ -210,8 +223,7 @@ def main():
 
     # ---- timed region: each step hashes one batch, encrypts one and
     # decrypts one ----
-    enc.profile(True)
-    dec.profile(True)
+    pre_e, pre_d = enc.profile_read(), dec.profile_read()
     enc.profile_reset()
     dec.profile_reset()
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
@@ -227,6 +239,8 @@ def main():
     elapsed = t1 - t0
     step_ms = [evs[i].elapsed_time(evs[i + 1]) for i in range(args.steps)]
     prof_e, prof_d = enc.profile_read(), dec.profile_read()
+    dispatch_window = {k: [pre_e[k][1] + pre_d[k][1], prof_e[k][1] + prof_d[k][1]] for k in V.KERNELS
+                       if prof_e[k][1] + prof_d[k][1]}
     enc.profile(False)
     dec.profile(False)
     # drain
@@ -276,26 +290,39 @@ def main():
     for k in kernels.values():
         k["share"] = k["total_ms"] / total_kernel_ms
 
-    # fused confusion + XOR kernel: algorithmic bytes = read P + read B +
-    # write C = 9wh per frame (D, 6(w+h) bytes, is negligible); one launch
-    # covers the whole batch.
-    def hbm_roof(name):
-        kk = kernels[name]
-        launches_per_step = kk["launches"] / args.steps
-        frames_per_launch = T / launches_per_step
-        bytes_per_launch = frames_per_launch * 9.0 * w * h
-        gbs = bytes_per_launch / (kk["avg_us"] * 1e-6) / 1e9
-        return {"kernel": name, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                "bytes_per_launch": bytes_per_launch, "frames_per_launch": frames_per_launch}
+    # Confusion + XOR.  Algorithmic bytes of the operation: read P, read B,
+    # write C = 9wh per frame (D, 6(w+h) bytes, is negligible).  Two-pass
+    # form: the row pass moves 6wh (read P, write S) and the column pass 9wh
+    # (read S and B, write C); the operation's roofline takes 9wh over the
+    # sum of both kernels' average launch times (each launch covers the same
+    # frames).  Single-pass form: one kernel, 9wh.
+    def frames_per_launch(name):
+        return T / (kernels[name]["launches"] / args.steps)
 
-    roof_enc = hbm_roof("confuse_xor_enc")
-    roof_dec = hbm_roof("confuse_xor_dec")
-    for roof in (roof_enc, roof_dec):
-        t = measured_traffic(roof["frames_per_launch"], w, h).get(roof["kernel"])
-        if t is not None:
-            roof["traffic"] = t["bytes_per_launch"]
-            roof["traffic_detail"] = t
+    def hbm_roof(names, bytes_per_frame):
+        fpl = frames_per_launch(names[0])
+        secs = sum(kernels[k]["avg_us"] for k in names) * 1e-6
+        bpl = fpl * bytes_per_frame
+        gbs = bpl / secs / 1e9
+        roof = {"kernel": " + ".join(names), "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": bpl, "frames_per_launch": fpl}
+        tr = [measured_traffic(fpl, w, h).get(k) for k in names]
+        if all(t is not None for t in tr):
+            roof["traffic"] = sum(t["bytes_per_launch"] for t in tr)
+            roof["traffic_detail"] = {k: t for k, t in zip(names, tr)}
+        return roof
+
+    two_pass = "col_shift_xor_enc" in kernels
+    if two_pass:
+        roof_enc = hbm_roof(["row_shift_enc", "col_shift_xor_enc"], 9.0 * w * h)
+        roof_dec = hbm_roof(["col_shift_xor_dec", "row_shift_dec"], 9.0 * w * h)
+        roof_kernels = [hbm_roof([k], b * w * h) for k, b in (("row_shift_enc", 6.0), ("col_shift_xor_enc", 9.0),
+                                                               ("col_shift_xor_dec", 9.0), ("row_shift_dec", 6.0))]
+    else:
+        roof_enc = hbm_roof(["confuse_xor_enc"], 9.0 * w * h)
+        roof_dec = hbm_roof(["confuse_xor_dec"], 9.0 * w * h)
+        roof_kernels = []
 
     # SHA-256: algorithmic 32-bit operations of FIPS 180-4 per 64-byte block
     # (rounds: Sigma1 5, Ch 3, T1 4 adds, Sigma0 5, Maj 4, T2 1, e 1, a 1 =
@@ -315,7 +342,7 @@ def main():
     second = None
     if args.second_n:
         n2 = args.second_n
-        scratch2 = max((L + 2 * (3 * w + 3 * h) + 64 * n2 + 3 * 256) * T + (64 << 20), 256 << 20)
+        scratch2 = V.vc_scratch_per_frame(w, h, n2) * T + (64 << 20)
         e2 = make_cipher(n2, scratch2)
         d2 = make_cipher(n2, scratch2)
 
@@ -411,6 +438,8 @@ def main():
                    "frames_per_step": T, "width": w, "height": h, "n": n, "gamma": gamma},
         "roofline": roof_enc,
         "roofline_dec": roof_dec,
+        "roofline_kernels": roof_kernels,
+        "dispatch_window": dispatch_window,
         "roofline_sha": roof_sha,
         "dominant_kernel": dominant,
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}

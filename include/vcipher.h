@@ -162,7 +162,9 @@ int cipher_status(vc_cipher *ctx, void *stream);
 
 /* Per-kernel timing with HIP events recorded on the launch stream around
  * every kernel launch.  Kernel ids: 0 sha256_subframes, 1 lhcs_chain,
- * 2 lhcs_keygen, 3 confuse_xor_enc, 4 confuse_xor_dec.  vc_profile_read
+ * 2 lhcs_keygen, 3 confuse_xor_enc, 4 confuse_xor_dec (single-pass
+ * confusion), 5 row_shift_enc, 6 col_shift_xor_enc, 7 col_shift_xor_dec,
+ * 8 row_shift_dec (two-pass confusion).  vc_profile_read
  * synchronises pending events and returns the summed milliseconds and the
  * launch count since profiling was enabled (or last reset). */
 int vc_profile_enable(vc_cipher *ctx, int enable);
@@ -188,6 +190,23 @@ const char *vc_kernel_name(int kernel_id);
  * Changing the slot count waits for the device.  Never changes output
  * bytes.  VC_EINVAL for out-of-range arguments. */
 int vc_set_overlap(vc_cipher *ctx, uint32_t parts, uint32_t side_streams, uint32_t scratch_slots);
+
+/* How the confusion + XOR of Sec. II-C (Eqs. 2-3, Algs. 3-7) runs:
+ * passes = 2 (default): a row pass (the d_h bit-row rotations, whole rows)
+ * and a column pass (the d_v rotations and the XOR with B, full-height
+ * strips), through an intermediate image in the scratch -- 15 bytes of
+ * HBM traffic per pixel, every access a whole aligned word of a coalesced
+ * run; passes = 1: one fused pass per strip (9 bytes per pixel at best, but
+ * randomly placed per-channel row windows, and byte-granular scattered
+ * writes when decrypting).  Both give identical bytes.  VC_EINVAL unless
+ * passes is 1 or 2. */
+int vc_set_confusion_passes(vc_cipher *ctx, uint32_t passes);
+
+/* Device scratch one w x h frame needs with worker count n (keystream B,
+ * distances D, iterates IR and the two-pass intermediate, each 256-byte
+ * aligned): a context's scratch_bytes / scratch_slots should hold the
+ * frames of the largest call (else calls are split into spans). */
+size_t vc_scratch_per_frame(uint32_t w, uint32_t h, uint32_t n);
 
 /* Strip width (pixels: 4, 8, 16, 32 or 64; 0 = automatic) and
  * threads per workgroup (256, 512 or 1024; 0 = automatic) of the

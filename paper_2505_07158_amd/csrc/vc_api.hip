@@ -109,6 +109,7 @@ struct vc_cipher {
     // tuning
     uint32_t strip = 0, threads = 0;
     int xcd_map = 1;
+    int passes = 2;  // confusion: 2 = row pass + column pass, 1 = single fused pass
     // overlap of the chain with keygen + confusion (streams at default
     // priority, created on first use so that idle contexts hold none)
     uint32_t parts = 3;
@@ -218,10 +219,15 @@ int stage_acquire(vc_cipher *ctx, size_t bytes, int *slot_out) {
 
 uint64_t frame_bytes(const vc_shape &s) { return 3ull * s.w * s.h; }
 
-uint64_t scratch_need(const vc_shape &s, uint32_t n) {
+// Scratch of one frame: B, D and IR for the key schedule (keysched), plus
+// the intermediate image of the two-pass confusion (two_pass).
+uint64_t scratch_need(const vc_shape &s, uint32_t n, bool keysched, bool two_pass) {
     const uint64_t L = frame_bytes(s);
     const uint64_t ND = 3ull * s.h + 3ull * s.w;
-    return align_up(L, 256) + align_up(2 * ND, 256) + align_up(64ull * n, 256);
+    uint64_t b = 0;
+    if (keysched) b += align_up(L, 256) + align_up(2 * ND, 256) + align_up(64ull * n, 256);
+    if (two_pass) b += align_up(L, 256);
+    return b;
 }
 
 bool overlaps(const uint8_t *a, uint64_t la, const uint8_t *b, uint64_t lb) {
@@ -231,12 +237,25 @@ bool overlaps(const uint8_t *a, uint64_t la, const uint8_t *b, uint64_t lb) {
 int check_shape(const vc_cipher *ctx, const vc_shape &s, int decrypt, bool uses_n) {
     if (s.c != 3 || s.w < 1 || s.h < 1 || s.w > kMaxDim || s.h > kMaxDim) return VC_EINVAL;
     if (uses_n && ctx->key.n > frame_bytes(s)) return VC_EINVAL;
-    if (confuse_max_strip(decrypt, s.h, ctx->lds_limit) == 0) return VC_EINVAL;
+    const uint32_t fits = ctx->passes == 2 ? shift_max_strip(s.h, ctx->lds_limit)
+                                           : confuse_max_strip(decrypt, s.h, ctx->lds_limit);
+    if (fits == 0) return VC_EINVAL;
     return VC_OK;
 }
 
 uint32_t pick_strip(const vc_cipher *ctx, int decrypt, uint32_t w, uint32_t h) {
     const uint32_t wcap = std::max<uint32_t>(4, (w + 3) / 4 * 4);
+    if (ctx->passes == 2) {
+        if (ctx->strip && ctx->strip <= wcap && shift_col_lds_bytes(h, ctx->strip) <= ctx->lds_limit)
+            return ctx->strip;
+        // widest strip that leaves room for two column-pass workgroups per CU
+        uint32_t half = 0, fits = 0;
+        for (uint32_t wt = 4; wt <= 64 && wt <= wcap; wt *= 2) {
+            if (shift_col_lds_bytes(h, wt) <= ctx->lds_limit / 2) half = wt;
+            if (shift_col_lds_bytes(h, wt) <= ctx->lds_limit) fits = wt;
+        }
+        return half ? half : fits;
+    }
     if (ctx->strip) {
         if (ctx->strip <= wcap && confuse_lds_bytes(decrypt, h, ctx->strip) <= ctx->lds_limit)
             return ctx->strip;
@@ -294,7 +313,9 @@ size_t slot_bytes(const vc_cipher *ctx) { return ctx->scratch_bytes / ctx->nslot
 int run_call(vc_cipher *ctx, const CallArgs &a) {
     const bool encrypting = a.op == Op::Encrypt || a.op == Op::EncryptHashed;
     const bool uses_chain = encrypting || a.op == Op::Decrypt || a.op == Op::DebugKeysched;
-    const bool uses_scratch = encrypting || a.op == Op::Decrypt;
+    const bool keysched_scratch = encrypting || a.op == Op::Decrypt;
+    const bool two_pass = ctx->passes == 2 && a.op != Op::Hash && a.op != Op::DebugKeysched;
+    const bool uses_scratch = keysched_scratch || two_pass;
     const int dec_kernel = (a.op == Op::Decrypt) || (a.op == Op::DebugConfuse && a.decrypt);
     const uint32_t n = ctx->key.n;
     const size_t count = a.count;
@@ -312,7 +333,7 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
             return VC_EINVAL;
         if (a.op == Op::DebugConfuse && (!a.dbgD[f] || !a.dbgB[f])) return VC_EINVAL;
         if (a.op == Op::DebugKeysched && (!a.kIR[f] || !a.kD[f] || !a.kB[f])) return VC_EINVAL;
-        if (uses_scratch && scratch_need(s, n) > slot_bytes(ctx)) return VC_ENOMEM;
+        if (uses_scratch && scratch_need(s, n, keysched_scratch, two_pass) > slot_bytes(ctx)) return VC_ENOMEM;
         if (uses_chain) {
             if (s.stream >= ctx->max_streams) return VC_EINVAL;
             auto it = seq_next.find(s.stream);
@@ -322,7 +343,7 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         }
     }
     if (count == 0) return VC_OK;
-    if (uses_chain) {
+    if (uses_chain || uses_scratch) {
         const hipError_t e = ensure_streams(ctx);
         if (e != hipSuccess) return map_err(e);
     }
@@ -340,7 +361,7 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         size_t b = 0;
         uint64_t used = 0;
         for (size_t f = 0; f < count; ++f) {
-            const uint64_t need = uses_scratch ? scratch_need(a.shapes[f], n) : 0;
+            const uint64_t need = uses_scratch ? scratch_need(a.shapes[f], n, keysched_scratch, two_pass) : 0;
             if (f > b && used + need > cap) {
                 spans.push_back({b, f});
                 b = f;
@@ -407,7 +428,12 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
             d.IR = nullptr;
             d.D = nullptr;
             d.B = nullptr;
-            if (uses_scratch) {
+            d.X = nullptr;
+            if (two_pass) {
+                d.X = ctx->d_scratch + off;
+                off += align_up(d.L, 256);
+            }
+            if (keysched_scratch) {
                 const uint64_t ND = 3ull * s.h + 3ull * s.w;
                 d.B = ctx->d_scratch + off;
                 off += align_up(d.L, 256);
@@ -481,6 +507,24 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
     ConfuseTuning tun;
     tun.threads = ctx->threads ? ctx->threads : 1024;
     tun.xcd_map = ctx->xcd_map;
+
+    // Confusion + XOR (or its inverse) of one shape group on stream ws.
+    auto confuse_group = [&](const Group &g, hipStream_t ws) {
+        tun.strip = pick_strip(ctx, dec_kernel, g.w, g.h);
+        if (!two_pass)
+            return timed(ctx, dec_kernel ? K_DEC : K_ENC, ws, [&] {
+                return launch_confuse(dec_kernel, d_desc, g.first, g.count, g.w, g.h, g.aligned, tun, ws);
+            });
+        for (int pass = 0; pass < 2; ++pass) {
+            const int kid = dec_kernel ? (pass == 0 ? K_COL_DEC : K_ROW_DEC) : (pass == 0 ? K_ROW_ENC : K_COL_ENC);
+            const hipError_t pe = timed(ctx, kid, ws, [&] {
+                return launch_shift(dec_kernel, pass, d_desc, g.first, g.count, g.w, g.h, g.aligned, tun,
+                                    ctx->lds_limit, ws);
+            });
+            if (pe != hipSuccess) return pe;
+        }
+        return hipSuccess;
+    };
 
     // ---- launches ----
     if (a.op == Op::Encrypt || a.op == Op::Hash) {
@@ -565,10 +609,7 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
             if (e != hipSuccess) return fail(e);
             if (a.op != Op::DebugKeysched) {
                 for (const Group &g : ch.groups) {
-                    tun.strip = pick_strip(ctx, dec_kernel, g.w, g.h);
-                    e = timed(ctx, dec_kernel ? K_DEC : K_ENC, ws, [&] {
-                        return launch_confuse(dec_kernel, d_desc, g.first, g.count, g.w, g.h, g.aligned, tun, ws);
-                    });
+                    e = confuse_group(g, ws);
                     if (e != hipSuccess) return fail(e);
                 }
             }
@@ -581,14 +622,37 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         if (e != hipSuccess) return map_err(e);
         if (uses_scratch) ctx->slot_next = (ctx->slot_next + nspans) % ctx->nslots;
     } else if (a.op == Op::DebugConfuse) {
+        // On the caller's stream; the two-pass intermediate takes scratch
+        // slots like any other call.
+        int cur_span = -1;
         for (const Chunk &ch : chunks) {
+            if (uses_scratch && static_cast<int>(ch.span) != cur_span) {
+                if (cur_span >= 0) {
+                    const uint32_t q = slot_of(static_cast<uint32_t>(cur_span));
+                    e = hipEventRecord(ctx->slot_ev[q][0], s);
+                    if (e != hipSuccess) return map_err(e);
+                    ctx->slot_live[q][0] = true;
+                }
+                cur_span = static_cast<int>(ch.span);
+                const uint32_t q = slot_of(ch.span);
+                for (int k = 0; k < kMaxSide; ++k) {
+                    if (!ctx->slot_live[q][k]) continue;
+                    e = hipStreamWaitEvent(s, ctx->slot_ev[q][k], 0);
+                    if (e != hipSuccess) return map_err(e);
+                    ctx->slot_live[q][k] = false;
+                }
+            }
             for (const Group &g : ch.groups) {
-                tun.strip = pick_strip(ctx, dec_kernel, g.w, g.h);
-                e = timed(ctx, dec_kernel ? K_DEC : K_ENC, s, [&] {
-                    return launch_confuse(dec_kernel, d_desc, g.first, g.count, g.w, g.h, g.aligned, tun, s);
-                });
+                e = confuse_group(g, s);
                 if (e != hipSuccess) return map_err(e);
             }
+        }
+        if (uses_scratch && cur_span >= 0) {
+            const uint32_t q = slot_of(static_cast<uint32_t>(cur_span));
+            e = hipEventRecord(ctx->slot_ev[q][0], s);
+            if (e != hipSuccess) return map_err(e);
+            ctx->slot_live[q][0] = true;
+            ctx->slot_next = (ctx->slot_next + nspans) % ctx->nslots;
         }
     }
     e = hipEventRecord(ctx->stage_ev[slot], s);
@@ -638,6 +702,10 @@ const char *vc_kernel_name(int kernel_id) {
     case K_KEYGEN: return "lhcs_keygen";
     case K_ENC: return "confuse_xor_enc";
     case K_DEC: return "confuse_xor_dec";
+    case K_ROW_ENC: return "row_shift_enc";
+    case K_COL_ENC: return "col_shift_xor_enc";
+    case K_COL_DEC: return "col_shift_xor_dec";
+    case K_ROW_DEC: return "row_shift_dec";
     default: return "";
     }
 }
@@ -710,7 +778,10 @@ int cipher_init(const vc_key *key, uint32_t max_streams, size_t scratch_bytes, v
             break;
         }
         ctx->lds_limit = static_cast<uint32_t>(lds);
-        if (confuse_configure(ctx->lds_limit) != hipSuccess) { rc = VC_EDEVICE; break; }
+        if (confuse_configure(ctx->lds_limit) != hipSuccess || shift_configure(ctx->lds_limit) != hipSuccess) {
+            rc = VC_EDEVICE;
+            break;
+        }
         try {
             ctx->next_seq.assign(max_streams, 0);
         } catch (...) {
@@ -923,6 +994,18 @@ int vc_set_overlap(vc_cipher *ctx, uint32_t parts, uint32_t side_streams, uint32
     ctx->parts = parts;
     ctx->nside = side_streams;
     return VC_OK;
+}
+
+int vc_set_confusion_passes(vc_cipher *ctx, uint32_t passes) {
+    if (!ctx || (passes != 1 && passes != 2)) return VC_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    ctx->passes = static_cast<int>(passes);
+    return VC_OK;
+}
+
+size_t vc_scratch_per_frame(uint32_t w, uint32_t h, uint32_t n) {
+    vc_shape s{w, h, 3, 0, 0};
+    return static_cast<size_t>(scratch_need(s, n, true, true));
 }
 
 int vc_set_tuning(vc_cipher *ctx, uint32_t strip_width, uint32_t threads, int xcd_map) {

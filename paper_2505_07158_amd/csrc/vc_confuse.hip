@@ -61,11 +61,6 @@ __device__ __forceinline__ void map_workgroup(uint32_t g, uint32_t nstrips, int 
     }
 }
 
-struct Geometry {
-    uint32_t w, h, W8, row_bytes;
-    float inv_h, inv_W8;
-};
-
 // LDS layout of both kernels: the strip S (h rows of RS bytes), then the
 // row distances d_h mod 8w (3h words), then the strip's column distances
 // d_v mod h (3 x (WT + 4) words).

@@ -25,6 +25,7 @@ struct FrameDesc {
     double *IR;          // 2n x 4 LHCS_m iterates
     uint16_t *D;         // 3h + 3w shift distances
     uint8_t *B;          // 3wh keystream bytes
+    uint8_t *X;          // 3wh intermediate of the two-pass confusion (S or T)
     uint32_t w, h;
     uint64_t L;          // 3wh
 };
@@ -44,7 +45,24 @@ struct ChainRec {
     double *IR;           // 2n x 4 LHCS_m iterates
 };
 
-enum KernelId { K_SHA = 0, K_CHAIN = 1, K_KEYGEN = 2, K_ENC = 3, K_DEC = 4, K_COUNT = 5 };
+enum KernelId {
+    K_SHA = 0,
+    K_CHAIN = 1,
+    K_KEYGEN = 2,
+    K_ENC = 3,       // single-pass confusion + XOR
+    K_DEC = 4,       // single-pass inverse
+    K_ROW_ENC = 5,   // two-pass: row shift
+    K_COL_ENC = 6,   // two-pass: column shift + XOR
+    K_COL_DEC = 7,   // two-pass: XOR + inverse column shift
+    K_ROW_DEC = 8,   // two-pass: inverse row shift
+    K_COUNT = 9
+};
+
+// Frame geometry of a confusion launch (all frames of a launch share it).
+struct Geometry {
+    uint32_t w, h, W8, row_bytes;  // W8 = 8w bits per channel row, row_bytes = 3w
+    float inv_h, inv_W8;           // reciprocals for the distance reductions
+};
 
 struct ConfuseTuning {
     uint32_t strip;      // pixels per strip (multiple of 4)
@@ -71,5 +89,13 @@ hipError_t launch_confuse(int decrypt, const FrameDesc *d_desc, uint32_t first, 
 uint32_t confuse_max_strip(int decrypt, uint32_t h, uint32_t lds_bytes);
 uint32_t confuse_lds_bytes(int decrypt, uint32_t h, uint32_t strip);
 hipError_t confuse_configure(uint32_t lds_limit);
+// Two-pass confusion (vc_shift.hip).  pass 0 then pass 1: encrypt = rows,
+// then columns + XOR; decrypt = XOR + columns, then rows.  Reads and writes
+// FrameDesc::X as the intermediate.
+hipError_t launch_shift(int decrypt, int pass, const FrameDesc *d_desc, uint32_t first, uint32_t count, uint32_t w,
+                        uint32_t h, bool aligned, const ConfuseTuning &t, uint32_t lds_limit, hipStream_t s);
+uint32_t shift_max_strip(uint32_t h, uint32_t lds_bytes);
+uint32_t shift_col_lds_bytes(uint32_t h, uint32_t strip);
+hipError_t shift_configure(uint32_t lds_limit);
 
 }  // namespace vc

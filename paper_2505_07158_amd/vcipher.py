@@ -20,7 +20,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvcipher.so")
 
 VC_OK, VC_EINVAL, VC_ENOMEM, VC_EDEVICE, VC_EORDER, VC_ENONFINITE, VC_EBUSY = 0, -1, -2, -3, -4, -5, -6
-KERNELS = ("sha256_subframes", "lhcs_chain", "lhcs_keygen", "confuse_xor_enc", "confuse_xor_dec")
+KERNELS = ("sha256_subframes", "lhcs_chain", "lhcs_keygen", "confuse_xor_enc", "confuse_xor_dec", "row_shift_enc",
+           "col_shift_xor_enc", "col_shift_xor_dec", "row_shift_dec")
 
 
 class VcKey(C.Structure):
@@ -67,6 +68,9 @@ def _load() -> C.CDLL:
     L.vc_profile_reset.argtypes = [vp]
     L.vc_set_tuning.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_int]
     L.vc_set_overlap.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_uint32]
+    L.vc_set_confusion_passes.argtypes = [vp, C.c_uint32]
+    L.vc_scratch_per_frame.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
+    L.vc_scratch_per_frame.restype = C.c_size_t
     L.vc_debug_confuse.argtypes = [vp, C.c_int, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape),
                                    C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
     L.vc_debug_keysched.argtypes = [vp, C.c_size_t, C.POINTER(VcShape), u8p, C.POINTER(vp),
@@ -75,7 +79,7 @@ def _load() -> C.CDLL:
                  "cipher_stream_reset",
                  "cipher_stream_get_state", "cipher_stream_set_state", "cipher_status",
                  "vc_profile_enable", "vc_profile_read", "vc_profile_reset", "vc_set_tuning",
-                 "vc_set_overlap",
+                 "vc_set_overlap", "vc_set_confusion_passes",
                  "vc_debug_confuse", "vc_debug_keysched", "vc_key_from_bytes"):
         getattr(L, name).restype = C.c_int
     return L
@@ -277,6 +281,14 @@ def vc_set_overlap(ctx: int, parts: int = 3, side_streams: int = 3, scratch_slot
     _check(lib.vc_set_overlap(C.c_void_p(ctx), parts, side_streams, scratch_slots), "vc_set_overlap")
 
 
+def vc_set_confusion_passes(ctx: int, passes: int = 2) -> None:
+    _check(lib.vc_set_confusion_passes(C.c_void_p(ctx), passes), "vc_set_confusion_passes")
+
+
+def vc_scratch_per_frame(w: int, h: int, n: int) -> int:
+    return int(lib.vc_scratch_per_frame(w, h, n))
+
+
 # --------------------------------------------------------------------------
 # convenience wrapper
 # --------------------------------------------------------------------------
@@ -417,3 +429,6 @@ class Cipher:
 
     def overlap(self, parts: int = 3, side_streams: int = 3, scratch_slots: int = 2) -> None:
         vc_set_overlap(self.ctx, parts, side_streams, scratch_slots)
+
+    def passes(self, passes: int = 2) -> None:
+        vc_set_confusion_passes(self.ctx, passes)

@@ -146,7 +146,8 @@ def test_small_scratch_processes_in_chunks():
     dev = require_gpu()
     kb = key_bytes(4)
     frames = SynthVideo(128, 96, seed=4).frames(7)
-    small = V().Cipher.from_bytes(kb, -1.0, 32, scratch_bytes=2 * 128 * 96 * 3 + 65536)
+    # two slots of one frame each: every frame is a span of its own
+    small = V().Cipher.from_bytes(kb, -1.0, 32, scratch_bytes=2 * (V().vc_scratch_per_frame(128, 96, 32) + 4096))
     big = V().Cipher.from_bytes(kb, -1.0, 32)
     C1, H1 = small.encrypt(to_dev(frames, dev))
     C2, H2 = big.encrypt(to_dev(frames, dev))
@@ -167,7 +168,7 @@ def test_overlap_settings_match_oracle(parts, side, slots):
     n = 6
     video = SynthVideo(96, 64, seed=12).frames(13)
     Cs, Hs, _ = oracle_stream(kb, -1.0, n, list(video))
-    per_frame = 18432 + 1024 + 512  # B, D and IR of one 96x64 frame at n = 6, 256-byte aligned
+    per_frame = V().vc_scratch_per_frame(96, 64, n)
     for scratch in (0, slots * (per_frame + per_frame // 2), slots * 2 * per_frame):
         c = V().Cipher.from_bytes(kb, -1.0, n, scratch_bytes=scratch)
         c.overlap(parts, side, slots)
@@ -208,7 +209,7 @@ def test_calls_on_alternating_streams_match_oracle(slots):
     n = 5
     video = SynthVideo(80, 48, seed=14).frames(15)
     Cs, Hs, _ = oracle_stream(kb, -1.0, n, list(video))
-    per = 3 * (80 * 48 * 3 + 256 + 2 * (3 * 80 + 3 * 48) + 256 + 64 * n + 256)
+    per = 3 * V().vc_scratch_per_frame(80, 48, n) + 4096  # one batch of 3 frames per slot
     src = to_dev(video, dev)
     enc = V().Cipher.from_bytes(kb, -1.0, n, scratch_bytes=per * slots)
     dec = V().Cipher.from_bytes(kb, -1.0, n, scratch_bytes=per * slots)

@@ -1,6 +1,7 @@
 """GPU parity of the confusion + XOR kernels and their inverse (Sec. II-C)
 against the oracle, byte for byte, with caller-supplied D and B through the
-C-ABI testing entry point (the same kernels encrypt_frames uses)."""
+C-ABI testing entry point (the same kernels encrypt_frames uses), for both
+the two-pass (row pass + column pass) and the single-pass form."""
 import itertools
 
 import numpy as np
@@ -13,7 +14,8 @@ from gpu_util import require_gpu, to_dev, to_np
 pytestmark = pytest.mark.gpu
 
 SHAPES = [(1, 1), (1, 4), (2, 3), (3, 1), (5, 7), (4, 4), (8, 12), (17, 5), (64, 64), (33, 100),
-          (100, 33), (480, 640), (481, 643), (720, 1280), (1080, 1920), (2, 2000), (2000, 3)]
+          (100, 33), (480, 640), (481, 643), (720, 1280), (1080, 1920), (2, 2000), (2000, 3),
+          (3, 56000)]  # a row longer than the LDS: the row pass reads global memory
 
 
 def case(rng, h, w):
@@ -23,11 +25,12 @@ def case(rng, h, w):
     return P, D, B
 
 
-@pytest.fixture(scope="module")
-def ctx():
+@pytest.fixture(scope="module", params=[2, 1], ids=["two_pass", "single_pass"])
+def ctx(request):
     require_gpu()
     from paper_2505_07158_amd import vcipher as V
     c = V.Cipher(V.vc_key_from_bytes(bytes(range(32)), -1.0, 4))
+    c.passes(request.param)
     yield c
     c.close()
 

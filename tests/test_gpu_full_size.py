@@ -24,8 +24,8 @@ def test_config3_full_size():
     kb = key_bytes(0)
     host = SynthVideo(w, h, seed=config_seed(3), pan=(3.0, 1.0)).frames(T)
     frames = torch.from_numpy(host).to(dev)
-    enc = V.Cipher.from_bytes(kb, gamma, n, scratch_bytes=(6_300_000 * T))
-    dec = V.Cipher.from_bytes(kb, gamma, n, scratch_bytes=(6_300_000 * T))
+    enc = V.Cipher.from_bytes(kb, gamma, n, scratch_bytes=2 * V.vc_scratch_per_frame(1920, 1080, n) * T)
+    dec = V.Cipher.from_bytes(kb, gamma, n, scratch_bytes=2 * V.vc_scratch_per_frame(1920, 1080, n) * T)
     C, H = enc.encrypt(frames)
     P = dec.decrypt(C, H)
     torch.cuda.synchronize()
