@@ -8,16 +8,16 @@ hot path over one batch of 300 frames: frame hash (vc_hash_frames), key
 schedule + confusion + XOR (encrypt_frames_hashed), and on a receiver
 context key schedule + inverse confusion (decrypt_frames).  The three run
 as a stream pipeline, the way a sender and a receiver overlap on a live
-link: in each step batch k is hashed, batch k-1 encrypted and batch k-2
+link: in each step batch k is hashed, batch k-1 encrypted and batch k-3
 decrypted, so every step does the full work of one batch.  Frames stay
 resident in HBM; the timed region contains only the library calls.  The
 same work without the pipeline (encrypt_frames then decrypt_frames) is
-reported beside it.
+reported beside it, and a second row repeats the pipeline at n = 256.
 
 Prints one JSON line: frames/s (value), per-kernel times from HIP events
 recorded around every launch inside the timed region, the HBM roofline of
-the fused confusion + XOR kernel, single-frame latency percentiles, and the
-CPU oracle timed on this host's cores on a bounded sample.
+the confusion + XOR step, single-frame latency percentiles, and the CPU
+oracle timed on this host's cores on a bounded sample.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1]
 """
@@ -52,9 +52,11 @@ def parse():
     ap.add_argument("--parts", type=int, default=3, help="sub-batches per call whose keygen and confusion "
                     "overlap the chain (1 = none)")
     ap.add_argument("--side", type=int, default=3, help="side streams per context for that overlap")
-    ap.add_argument("--slots", type=int, default=2, help="scratch slots per context (one batch each)")
+    ap.add_argument("--slots", type=int, default=3, help="scratch slots per context (one batch each)")
+    ap.add_argument("--lag-enc", type=int, default=1, help="batches between hashing and encrypting a batch")
+    ap.add_argument("--lag-dec", type=int, default=3, help="batches between hashing and decrypting a batch")
     ap.add_argument("--hw-queues", type=int, default=16,
-                    help="GPU_MAX_HW_QUEUES for this process (0 = HIP's default of 4): the benchmark runs 5 streams "
+                    help="GPU_MAX_HW_QUEUES for this process (0 = HIP default of 4): the benchmark runs 6 streams "
                     "of its own and 4 per context, and streams sharing a hardware queue are serialised")
     ap.add_argument("--latency-iters", type=int, default=30)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-oracle sample")
@@ -142,16 +144,21 @@ def main():
     frames = torch.from_numpy(host).to(dev)
     # Three-stage stream pipeline (a sender that hashes frames as they come
     # and encrypts them as the key chain allows, and a receiver): batch k is
-    # hashed while batch k-1 is encrypted and batch k-2 decrypted.  Sender
-    # and receiver alternate between two streams each, so that the key
-    # chain of one batch runs while the previous batch's keygen and
-    # confusion finish (the library orders the chain and its scratch slots
-    # across streams).  Hash and ciphertext buffers rotate over four slots.
-    NB = 4
+    # hashed while batch k-LE is encrypted and batch k-LD decrypted (defaults
+    # 1 and 3).  Hashing,
+    # encryption and decryption each alternate between two streams, so that
+    # one batch's SHA-256 overlaps the next one's and the key chain of one
+    # batch runs while the previous batch's keygen and confusion finish (the
+    # library orders the chain and its scratch slots across streams).  Hash
+    # and ciphertext buffers rotate over four slots.
+    LE, LD = args.lag_enc, args.lag_dec
+    if not 1 <= LE < LD:
+        sys.exit("need 1 <= --lag-enc < --lag-dec")
+    NB = LD + 2
     hbuf = [torch.empty((T, 32), dtype=torch.uint8, device=dev) for _ in range(NB)]
     cbuf = [torch.empty_like(frames) for _ in range(NB)]
     plain = [torch.empty_like(frames) for _ in range(2)]
-    s_hash = torch.cuda.Stream()
+    s_hash = [torch.cuda.Stream() for _ in range(2)]
     s_enc = [torch.cuda.Stream() for _ in range(2)]
     s_dec = [torch.cuda.Stream() for _ in range(2)]
     hashed = [torch.cuda.Event() for _ in range(NB)]
@@ -179,9 +186,10 @@ def main():
 
     def stage_hash(k):
         b = k % NB
-        s_hash.wait_event(freed[b])          # the receiver is done with slot b
-        enc.hash(frames, stream=s_hash, out=hbuf[b])
-        hashed[b].record(s_hash)
+        sh = s_hash[k % 2]
+        sh.wait_event(freed[b])          # the receiver is done with slot b
+        enc.hash(frames, stream=sh, out=hbuf[b])
+        hashed[b].record(sh)
 
     def stage_enc(k):
         b, st = k % NB, s_enc[k % 2]
@@ -211,13 +219,17 @@ def main():
     first_c = cbuf[0][:sample_frames].cpu().numpy()
     first_h = hbuf[0].cpu().numpy()
 
+    def step(k):
+        stage_hash(k)
+        if k - LE >= 1:
+            stage_enc(k - LE)
+        if k - LD >= 1:
+            stage_dec(k - LD)
+
     # ---- fill the pipeline, warm up ----
-    stage_hash(1)
-    stage_hash(2)
-    stage_enc(1)
-    k = 3
-    for _ in range(args.warmup):
-        stage_hash(k); stage_enc(k - 1); stage_dec(k - 2)
+    k = 1
+    while k <= LD + args.warmup:
+        step(k)
         k += 1
     torch.cuda.synchronize()
 
@@ -229,10 +241,10 @@ def main():
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    evs[0].record(s_dec[(k - 3) % 2])
+    evs[0].record(s_dec[(k - 1 - LD) % 2])
     for i in range(args.steps):
-        stage_hash(k); stage_enc(k - 1); stage_dec(k - 2)
-        evs[i + 1].record(s_dec[(k - 2) % 2])
+        step(k)
+        evs[i + 1].record(s_dec[(k - LD) % 2])
         k += 1
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -244,7 +256,10 @@ def main():
     enc.profile(False)
     dec.profile(False)
     # drain
-    stage_enc(k - 1); stage_dec(k - 2); stage_dec(k - 1)
+    for j in range(k - LE, k):
+        stage_enc(j)
+    for j in range(k - LD, k):
+        stage_dec(j)
     torch.cuda.synchronize()
     roundtrip_ok = roundtrip_ok and bool(torch.equal(plain[0], frames)) and bool(torch.equal(plain[1], frames))
     assert enc.status() == 0 and dec.status() == 0
@@ -348,9 +363,10 @@ def main():
 
         def step2(k):
             b = k % NB
-            s_hash.wait_event(freed[b])
-            e2.hash(frames, stream=s_hash, out=hbuf[b])
-            hashed[b].record(s_hash)
+            sh = s_hash[k % 2]
+            sh.wait_event(freed[b])
+            e2.hash(frames, stream=sh, out=hbuf[b])
+            hashed[b].record(sh)
             se, sd = s_enc[k % 2], s_dec[k % 2]
             se.wait_event(hashed[b])
             e2.encrypt_hashed(frames, hbuf[b], out=cbuf[b], stream=se)

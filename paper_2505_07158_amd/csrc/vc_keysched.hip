@@ -283,7 +283,7 @@ __global__ __launch_bounds__(128) void lhcs_keygen(const FrameDesc *__restrict__
     for (uint32_t blk = 0; blk < nblk; ++blk) {
         __syncthreads();
         if (!live) continue;
-#pragma unroll
+#pragma unroll 1
         for (uint32_t j = 0; j < kKgHalf; ++j) {
             const uint64_t s = static_cast<uint64_t>(blk) * kKgHalf + j;
             if (s >= steps) break;
