@@ -40,6 +40,14 @@ VALU_PEAK_GOPS = 256 * 64 * 2.4  # 32-bit lane ops/s (256 CUs x 64 lanes x 2.4 G
 def parse():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--workload", choices=["video", "batched", "serving"], default="video",
+                    help="video: 300 1080p frames per step (default); batched: 48 streams of uneven shapes; "
+                    "serving: the request-loop trace")
+    ap.add_argument("--duration", type=float, default=10.0, help="serving: seconds of arrival trace")
+    ap.add_argument("--hbm-budget-gb", type=float, default=16.0, help="serving: admission budget")
+    ap.add_argument("--max-batch", type=int, default=256, help="serving: frames per batch at most")
+    ap.add_argument("--plain-frames", type=int, default=400, help="serving: arrivals replayed one frame per launch")
+    ap.add_argument("--inflight", type=int, default=3, help="serving: batches of a kind in flight (device streams)")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=32, help="worker count (key material)")
@@ -114,6 +122,217 @@ def pct(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=float), q))
 
 
+def run_serving(args) -> None:
+    """Serving workload: 64 streams (seed 5000) with frame rates from
+    {24, 30, 60} and resolutions from {640x480, 1280x720, 1920x1080,
+    3840x2160}; Poisson arrivals at each stream's frame rate for
+    --duration seconds; 30 % of the streams are decrypt streams (their
+    ciphertext and hashes come from a separate sender context with the same
+    key).  The continuous-batching loop (paper_2505_07158_amd.serving) runs
+    the trace, then the first --plain-frames arrivals run with one frame per
+    launch (the plain per-frame path).  Reports p50/p99 arrival-to-completion latency, per
+    resolution too, delivered frames/s and the delay rate (frames later than
+    one frame interval, 1000/FPS ms)."""
+    import numpy as np
+    import torch
+
+    from paper_2505_07158_amd import vcipher as V
+    from paper_2505_07158_amd.serving import GpuBackend, Request, Scheduler
+    from workload.synth import key_bytes
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    rng = np.random.default_rng(5000)
+    S, n, gamma, kb = 64, args.n, -1.0, key_bytes(0)
+    res_set = [(640, 480), (1280, 720), (1920, 1080), (3840, 2160)]
+    fps_set = [24, 30, 60]
+    streams = []
+    for s in range(S):
+        w, h = res_set[rng.integers(len(res_set))]
+        streams.append({"w": int(w), "h": int(h), "fps": int(fps_set[rng.integers(len(fps_set))]),
+                        "kind": "dec" if rng.random() < 0.3 else "enc"})
+    # Poisson arrival trace
+    trace = []
+    for s, st in enumerate(streams):
+        t, seq = float(rng.exponential(1.0 / st["fps"])), 0
+        while t < args.duration:
+            trace.append((t, s, seq))
+            seq += 1
+            t += float(rng.exponential(1.0 / st["fps"]))
+    trace.sort()
+    # frame pools (the cipher is data-oblivious: timing does not depend on content)
+    P = 4
+    pool = []
+    for st in streams:
+        fr = torch.empty((P, st["h"], st["w"], 3), dtype=torch.uint8, device=dev)
+        fr.random_(0, 256)
+        pool.append(fr)
+    budget = int(args.hbm_budget_gb * (1 << 30))
+
+    def one_run(trace, max_batch, max_inflight):
+        be = GpuBackend(kb, gamma, n, max_streams=S, scratch_bytes=budget, overlap=(args.parts, args.side, 2),
+                        device_streams=max_inflight)
+        dec_src = {}
+        sender = V.Cipher.from_bytes(kb, gamma, n, max_streams=S, scratch_bytes=max(budget // 4, 1 << 30))
+        for s, st in enumerate(streams):
+            if st["kind"] == "dec":
+                C, H = sender.encrypt(pool[s], streams=[s] * P)
+                dec_src[s] = (C, H)
+        torch.cuda.synchronize()
+        sender.close()
+        sched = Scheduler(be.launch, hbm_budget=budget, max_inflight=max_inflight, max_batch=max_batch,
+                          batch_class=lambda r: (streams[r.stream]["w"], streams[r.stream]["h"]))
+        reqs = []
+        i = 0
+        t0 = time.perf_counter()
+        while i < len(trace) or not sched.idle():
+            now = time.perf_counter() - t0
+            while i < len(trace) and trace[i][0] <= now:
+                ta, s, seq = trace[i]
+                st = streams[s]
+                if st["kind"] == "enc":
+                    frame, hashes = pool[s][seq % P], torch.empty(32, dtype=torch.uint8, device=dev)
+                else:
+                    frame, hashes = dec_src[s][0][seq % P], dec_src[s][1][seq % P]
+                r = Request(stream=s, seq=seq, kind=st["kind"], frame=frame, out=torch.empty_like(frame),
+                            hashes=hashes, nbytes=be.footprint(st["w"], st["h"]), arrival=t0 + ta)
+                reqs.append(r)
+                sched.submit(r)
+                i += 1
+            if not sched.pump():
+                time.sleep(0.0001)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        # decrypt requests whose ciphertext matches their sequence number
+        ok = all(torch.equal(r.out, pool[r.stream][r.seq]) for r in reqs if r.kind == "dec" and r.seq < P)
+        status_ok = be.ctx["enc"].status() == 0 and be.ctx["dec"].status() == 0
+        be.close()
+        lat = np.array([1000.0 * r.latency for r in reqs])
+        late = np.array([1000.0 * r.latency > 1000.0 / streams[r.stream]["fps"] for r in reqs])
+        per_res = {}
+        for (w, h) in res_set:
+            sel = [k for k, r in enumerate(reqs) if (streams[r.stream]["w"], streams[r.stream]["h"]) == (w, h)]
+            if sel:
+                per_res[f"{w}x{h}"] = {"frames": len(sel), "p50_ms": round(float(np.percentile(lat[sel], 50)), 3),
+                                       "p99_ms": round(float(np.percentile(lat[sel], 99)), 3),
+                                       "delay_rate": round(float(late[sel].mean()), 4)}
+        sizes = [b for _, b in sched.batches]
+        return {"frames": len(reqs), "wall_s": round(wall, 3), "frames_per_s": round(len(reqs) / wall, 1),
+                "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "delay_rate": round(float(late.mean()), 4), "per_resolution": per_res, "batches": len(sizes),
+                "mean_batch": round(float(np.mean(sizes)), 2), "max_batch_seen": int(max(sizes)),
+                "decrypt_check_ok": bool(ok), "status_ok": bool(status_ok)}
+
+    batched = one_run(trace, args.max_batch, args.inflight)
+    # The plain per-frame path cannot keep up with the offered load; it runs
+    # the first --plain-frames arrivals of the same trace.
+    plain = one_run(trace[:args.plain_frames], 1, 1)
+    offered = len(trace) / args.duration
+    line = {"metric": "serving: p50/p99 arrival-to-completion latency (ms), frames/s", "value": batched["p99_ms"],
+            "unit": "ms (p99)", "n_gpus": 1, "higher_is_better": False, "dtype": "u8", "data": "synthetic",
+            "config": {"workload": f"serving, {S} streams, Poisson arrivals at 24/30/60 FPS, resolutions "
+                                   "640x480/1280x720/1920x1080/3840x2160, 30% decrypt streams, "
+                                   f"{args.duration} s trace", "n": n, "offered_frames_per_s": round(offered, 1),
+                       "hbm_budget_gb": args.hbm_budget_gb, "max_batch": args.max_batch,
+                       "inflight_batches_per_kind": args.inflight, "batch_class": "resolution"},
+            "continuous_batching": batched, "plain_per_frame": plain}
+    print(json.dumps(line), flush=True)
+
+
+def run_batched(args) -> None:
+    """Batched uneven shapes: 48 streams, 16 each at 640x480, 1280x720 and
+    1920x1080, 8 frames per stream per batch (384 frames, 1.27 GB of
+    plaintext).  One step encrypts one batch in one call and decrypts it in
+    one call on a receiver context; consecutive batches alternate between
+    two sender and two receiver streams.  The same frames through the plain
+    per-frame path (one call per frame) are timed beside it."""
+    import numpy as np
+    import torch
+
+    from paper_2505_07158_amd import vcipher as V
+    from workload.synth import key_bytes
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    n, gamma, kb = args.n, -1.0, key_bytes(0)
+    shapes = [(640, 480)] * 16 + [(1280, 720)] * 16 + [(1920, 1080)] * 16
+    F = 8
+    pool = []
+    for s_, (w, h) in enumerate(shapes):
+        t = torch.empty((F, h, w, 3), dtype=torch.uint8, device=dev)
+        t.random_(0, 256)
+        pool.append(t)
+    frames = [pool[s_][f] for s_ in range(len(shapes)) for f in range(F)]
+    sids = [s_ for s_ in range(len(shapes)) for _ in range(F)]
+    NF = len(frames)
+    per_batch = sum(V.vc_scratch_per_frame(w, h, n) for (w, h) in shapes) * F + (64 << 20)
+    enc = V.Cipher.from_bytes(kb, gamma, n, max_streams=len(shapes), scratch_bytes=per_batch * 2)
+    dec = V.Cipher.from_bytes(kb, gamma, n, max_streams=len(shapes), scratch_bytes=per_batch * 2)
+    NB = 3
+    cbuf = [[torch.empty_like(x) for x in frames] for _ in range(NB)]
+    pbuf = [[torch.empty_like(x) for x in frames] for _ in range(2)]
+    hbuf = [torch.empty((NF, 32), dtype=torch.uint8, device=dev) for _ in range(NB)]
+    s_e = [torch.cuda.Stream() for _ in range(2)]
+    s_d = [torch.cuda.Stream() for _ in range(2)]
+    ready = [torch.cuda.Event() for _ in range(NB)]
+    freed = [torch.cuda.Event() for _ in range(NB)]
+    seq = {"e": 0, "d": 0}
+
+    def step(k):
+        b = k % NB
+        se, sd = s_e[k % 2], s_d[k % 2]
+        se.wait_event(freed[b])
+        V.encrypt_frames(enc.ctx, frames, sids, [seq["e"] + f % F for f in range(NF)], hbuf[b], cbuf[b], se)
+        ready[b].record(se)
+        sd.wait_event(ready[b])
+        V.decrypt_frames(dec.ctx, cbuf[b], sids, [seq["d"] + f % F for f in range(NF)], hbuf[b], pbuf[k % 2], sd)
+        freed[b].record(sd)
+        seq["e"] += F
+        seq["d"] += F
+
+    step(0)                     # batch 0, kept for the plain-path comparison
+    torch.cuda.synchronize()
+    c0 = [x.clone() for x in cbuf[0]]
+    k = 1
+    for _ in range(args.warmup):
+        step(k)
+        k += 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(k)
+        k += 1
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ok = all(torch.equal(pbuf[(k - 1) % 2][i], frames[i]) for i in range(NF))
+    # plain per-frame path: the next batch, one call per frame and direction
+    e1 = V.Cipher.from_bytes(kb, gamma, n, max_streams=len(shapes))
+    d1 = V.Cipher.from_bytes(kb, gamma, n, max_streams=len(shapes))
+    c1 = [torch.empty_like(x) for x in frames]
+    p1 = [torch.empty_like(x) for x in frames]
+    h1 = torch.empty((NF, 32), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for i in range(NF):
+        V.encrypt_frames(e1.ctx, [frames[i]], [sids[i]], [i % F], h1[i:i + 1], [c1[i]], s_e[0])
+        V.decrypt_frames(d1.ctx, [c1[i]], [sids[i]], [i % F], h1[i:i + 1], [p1[i]], s_e[0])
+    torch.cuda.synchronize()
+    el1 = time.perf_counter() - t1
+    ok1 = all(torch.equal(p1[i], frames[i]) for i in range(NF))
+    same = all(torch.equal(c1[i], c0[i]) for i in range(NF))  # batch 0 of the batched run: same frames and seqs
+    assert enc.status() == 0 and dec.status() == 0
+    line = {"metric": "batched uneven shapes: frames/s (encrypt + decrypt)", "value": round(NF * args.steps / el, 1),
+            "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": round(1000 * el / args.steps, 3), "higher_is_better": True, "dtype": "u8",
+            "data": "synthetic", "config": {"workload": "48 streams (16 x 640x480, 16 x 1280x720, 16 x 1920x1080), "
+                                            "8 frames per stream per batch, one encrypt_frames + one decrypt_frames "
+                                            "call per batch", "n": n, "frames_per_batch": NF},
+            "plain_per_frame": {"value": round(NF / el1, 1), "unit": "frames/s", "calls": 2 * NF},
+            "speedup_vs_plain": round((NF * args.steps / el) / (NF / el1), 2),
+            "roundtrip_ok": bool(ok and ok1), "plain_equals_batched": bool(same)}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -121,11 +340,17 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path (streams would shard "
               "across GPUs with no collective; see the design notes).  Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
-
     if args.hw_queues:
         if not 1 <= args.hw_queues <= 32:
             sys.exit("--hw-queues must be in 1..32")
         os.environ["GPU_MAX_HW_QUEUES"] = str(args.hw_queues)
+    if args.workload == "serving":
+        run_serving(args)
+        return
+    if args.workload == "batched":
+        run_batched(args)
+        return
+
     import numpy as np
     import torch
 
@@ -264,6 +489,27 @@ def main():
     roundtrip_ok = roundtrip_ok and bool(torch.equal(plain[0], frames)) and bool(torch.equal(plain[1], frames))
     assert enc.status() == 0 and dec.status() == 0
 
+    # ---- the next batch once more, one call at a time and without the
+    # in-call overlap (nothing else on the GPU): kernel times in isolation ----
+    for c in (enc, dec):
+        c.overlap(1, 0, args.slots)
+    enc.profile(True)
+    dec.profile(True)
+    enc.profile_reset()
+    dec.profile_reset()
+    for stage in (stage_hash, stage_enc, stage_dec):
+        stage(k)
+        torch.cuda.synchronize()
+    iso_e, iso_d = enc.profile_read(), dec.profile_read()
+    enc.profile(False)
+    dec.profile(False)
+    kernels_iso = {}
+    for name in V.KERNELS:
+        ms = iso_e[name][0] + iso_d[name][0]
+        cnt = iso_e[name][1] + iso_d[name][1]
+        if cnt:
+            kernels_iso[name] = {"avg_us": round(1000.0 * ms / cnt, 1), "launches": cnt}
+
     # ---- reference: the same work without the pipeline (encrypt_frames,
     # then decrypt_frames on the receiver's stream, double-buffered) ----
     unpiped = None
@@ -311,12 +557,11 @@ def main():
     # (read S and B, write C); the operation's roofline takes 9wh over the
     # sum of both kernels' average launch times (each launch covers the same
     # frames).  Single-pass form: one kernel, 9wh.
-    def frames_per_launch(name):
-        return T / (kernels[name]["launches"] / args.steps)
-
-    def hbm_roof(names, bytes_per_frame):
-        fpl = frames_per_launch(names[0])
-        secs = sum(kernels[k]["avg_us"] for k in names) * 1e-6
+    def hbm_roof(names, bytes_per_frame, table=None, launches_per_batch=None):
+        table = table or kernels
+        lpb = launches_per_batch or table[names[0]]["launches"] / args.steps
+        fpl = T / lpb
+        secs = sum(table[k]["avg_us"] for k in names) * 1e-6
         bpl = fpl * bytes_per_frame
         gbs = bpl / secs / 1e9
         roof = {"kernel": " + ".join(names), "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
@@ -334,10 +579,13 @@ def main():
         roof_dec = hbm_roof(["col_shift_xor_dec", "row_shift_dec"], 9.0 * w * h)
         roof_kernels = [hbm_roof([k], b * w * h) for k, b in (("row_shift_enc", 6.0), ("col_shift_xor_enc", 9.0),
                                                                ("col_shift_xor_dec", 9.0), ("row_shift_dec", 6.0))]
+        roof_iso = hbm_roof(["row_shift_enc", "col_shift_xor_enc"], 9.0 * w * h, kernels_iso,
+                            kernels_iso["col_shift_xor_enc"]["launches"])
     else:
         roof_enc = hbm_roof(["confuse_xor_enc"], 9.0 * w * h)
         roof_dec = hbm_roof(["confuse_xor_dec"], 9.0 * w * h)
         roof_kernels = []
+        roof_iso = hbm_roof(["confuse_xor_enc"], 9.0 * w * h, kernels_iso, kernels_iso["confuse_xor_enc"]["launches"])
 
     # SHA-256: algorithmic 32-bit operations of FIPS 180-4 per 64-byte block
     # (rounds: Sigma1 5, Ch 3, T1 4 adds, Sigma0 5, Maj 4, T2 1, e 1, a 1 =
@@ -455,6 +703,8 @@ def main():
         "roofline": roof_enc,
         "roofline_dec": roof_dec,
         "roofline_kernels": roof_kernels,
+        "roofline_isolated": roof_iso,
+        "kernels_isolated": kernels_iso,
         "dispatch_window": dispatch_window,
         "roofline_sha": roof_sha,
         "dominant_kernel": dominant,

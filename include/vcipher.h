@@ -208,6 +208,18 @@ int vc_set_confusion_passes(vc_cipher *ctx, uint32_t passes);
  * frames of the largest call (else calls are split into spans). */
 size_t vc_scratch_per_frame(uint32_t w, uint32_t h, uint32_t n);
 
+/* Autotuner: time the strip-tiled confusion pass (the column pass of the
+ * two-pass form, or the single pass) for w x h frames, `frames` per launch
+ * (1..4096), over every strip width the LDS holds and 256/512/1024
+ * threads, on buffers it allocates and frees itself (contents arbitrary:
+ * the kernels are data-oblivious), and remember the fastest for this
+ * shape, direction (decrypt 0/1) and pass count.  Later calls use it unless
+ * vc_set_tuning fixed a tiling.  Writes the choice to *strip_out and
+ * *threads_out when not NULL.  Synchronous.  VC_EINVAL for an unsupported
+ * shape, VC_ENOMEM / VC_EDEVICE on device failures. */
+int vc_autotune(vc_cipher *ctx, int decrypt, uint32_t w, uint32_t h, uint32_t frames, uint32_t *strip_out,
+                uint32_t *threads_out);
+
 /* Strip width (pixels: 4, 8, 16, 32 or 64; 0 = automatic) and
  * threads per workgroup (256, 512 or 1024; 0 = automatic) of the
  * confusion kernels, and whether workgroups are mapped so that all strips

@@ -108,6 +108,9 @@ struct vc_cipher {
     int ring = 0;
     // tuning
     uint32_t strip = 0, threads = 0;
+    // autotuned (strip, threads) per (w, h, decrypt, passes); used when no
+    // fixed tuning is set
+    std::map<std::tuple<uint32_t, uint32_t, int, int>, std::pair<uint32_t, uint32_t>> tuned;
     int xcd_map = 1;
     int passes = 2;  // confusion: 2 = row pass + column pass, 1 = single fused pass
     // overlap of the chain with keygen + confusion (streams at default
@@ -511,6 +514,14 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
     // Confusion + XOR (or its inverse) of one shape group on stream ws.
     auto confuse_group = [&](const Group &g, hipStream_t ws) {
         tun.strip = pick_strip(ctx, dec_kernel, g.w, g.h);
+        tun.threads = ctx->threads ? ctx->threads : 1024;
+        if (!ctx->strip && !ctx->threads) {
+            auto it = ctx->tuned.find(std::make_tuple(g.w, g.h, dec_kernel, ctx->passes));
+            if (it != ctx->tuned.end()) {
+                tun.strip = it->second.first;
+                tun.threads = it->second.second;
+            }
+        }
         if (!two_pass)
             return timed(ctx, dec_kernel ? K_DEC : K_ENC, ws, [&] {
                 return launch_confuse(dec_kernel, d_desc, g.first, g.count, g.w, g.h, g.aligned, tun, ws);
@@ -993,6 +1004,95 @@ int vc_set_overlap(vc_cipher *ctx, uint32_t parts, uint32_t side_streams, uint32
     }
     ctx->parts = parts;
     ctx->nside = side_streams;
+    return VC_OK;
+}
+
+int vc_autotune(vc_cipher *ctx, int decrypt, uint32_t w, uint32_t h, uint32_t frames, uint32_t *strip_out,
+                uint32_t *threads_out) {
+    if (!ctx || frames < 1 || frames > 4096) return VC_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return VC_EDEVICE;
+    const vc_shape shape{w, h, 3, 0, 0};
+    int rc = check_shape(ctx, shape, decrypt ? 1 : 0, false);
+    if (rc) return rc;
+    const uint64_t L = frame_bytes(shape), ND = 3ull * h + 3ull * w;
+    const uint64_t Lp = align_up(L, 256), Dp = align_up(2 * ND, 256);
+    uint8_t *buf = nullptr;
+    FrameDesc *d_desc = nullptr;
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    const uint64_t total = frames * (4 * Lp + Dp);
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&buf), total);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&d_desc), sizeof(FrameDesc) * frames);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    uint32_t best_strip = 0, best_threads = 0;
+    if (e == hipSuccess) {
+        // frames, keystream and an intermediate image (contents do not matter:
+        // the kernels are data-oblivious); distances pseudorandom
+        std::vector<FrameDesc> desc(frames);
+        std::vector<uint16_t> D(ND);
+        uint32_t x = 0x9E3779B9u;
+        for (auto &v : D) {
+            x = x * 1664525u + 1013904223u;
+            v = static_cast<uint16_t>(x >> 16);
+        }
+        for (uint32_t f = 0; f < frames && e == hipSuccess; ++f) {
+            uint8_t *base = buf + f * (4 * Lp + Dp);
+            desc[f] = FrameDesc{base, base + Lp, nullptr, nullptr, reinterpret_cast<uint16_t *>(base + 4 * Lp),
+                                base + 2 * Lp, base + 3 * Lp, w, h, L};
+            e = hipMemcpyAsync(base + 4 * Lp, D.data(), 2 * ND, hipMemcpyHostToDevice, st);
+        }
+        if (e == hipSuccess) e = hipMemsetAsync(buf, 0x5A, frames * (4 * Lp), st);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(d_desc, desc.data(), sizeof(FrameDesc) * frames, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        const bool aligned = (w % 4) == 0;
+        const uint32_t wcap = std::max<uint32_t>(4, (w + 3) / 4 * 4);
+        float best = 1e30f;
+        for (uint32_t wt = 4; wt <= 64 && e == hipSuccess; wt *= 2) {
+            if (wt > wcap) break;
+            const uint32_t lds = ctx->passes == 2 ? shift_col_lds_bytes(h, wt) : confuse_lds_bytes(decrypt, h, wt);
+            if (lds > ctx->lds_limit) continue;
+            for (uint32_t nt : {256u, 512u, 1024u}) {
+                ConfuseTuning t;
+                t.strip = wt;
+                t.threads = nt;
+                t.xcd_map = ctx->xcd_map;
+                // the strip-tiled pass only: the row pass does not depend on the tiling
+                auto run = [&] {
+                    if (ctx->passes == 2)
+                        return launch_shift(decrypt, decrypt ? 0 : 1, d_desc, 0, frames, w, h, aligned, t,
+                                            ctx->lds_limit, st);
+                    return launch_confuse(decrypt, d_desc, 0, frames, w, h, aligned, t, st);
+                };
+                e = run();  // warm-up
+                if (e == hipSuccess) e = hipEventRecord(e0, st);
+                for (int r = 0; r < 3 && e == hipSuccess; ++r) e = run();
+                if (e == hipSuccess) e = hipEventRecord(e1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e == hipSuccess && ms < best) {
+                    best = ms;
+                    best_strip = wt;
+                    best_threads = nt;
+                }
+            }
+        }
+    }
+    if (e1) (void)hipEventDestroy(e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (st) (void)hipStreamDestroy(st);
+    if (d_desc) (void)hipFree(d_desc);
+    if (buf) (void)hipFree(buf);
+    if (e != hipSuccess) return map_err(e);
+    if (!best_strip) return VC_EINVAL;
+    ctx->tuned[std::make_tuple(w, h, decrypt ? 1 : 0, ctx->passes)] = {best_strip, best_threads};
+    if (strip_out) *strip_out = best_strip;
+    if (threads_out) *threads_out = best_threads;
     return VC_OK;
 }
 

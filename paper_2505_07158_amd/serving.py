@@ -1,0 +1,217 @@
+"""Continuous-batching request loop over the cipher library.
+
+Encrypt and decrypt requests for many video streams arrive at their own
+times.  The loop keeps the key state and scratch resident on the device (one
+sender context for encrypt requests, one receiver context for decrypt
+requests), and whenever fewer than ``max_inflight`` batches of a kind are on
+the GPU it launches the next batch from the requests that have arrived:
+
+* admission in arrival order, by device-memory footprint: a request holds
+  its input, its output and its per-frame scratch while in flight, and the
+  sum over in-flight requests stays within ``hbm_budget`` (a request larger
+  than the whole budget is admitted alone);
+* per-stream order: a stream's frame t+1 is never launched before frame t
+  (the chain of the paper's Alg. 1 is serial per stream), and frames of one
+  stream in one batch go in sequence order;
+* a batch is one library call (encrypt_frames or decrypt_frames) over any
+  mix of streams; with a ``batch_class`` (e.g. the resolution) only
+  requests of one class share a batch, so small frames do not wait for the
+  serial SHA-256 and key schedule of large ones; consecutive batches of a
+  kind go to rotating device streams, so they overlap on the device and a
+  batch's key chain runs while earlier batches' keygen and confusion
+  finish.
+
+The scheduling core (:class:`Scheduler`) is plain Python over an abstract
+backend, so that its admission and ordering rules are testable on the CPU;
+:class:`GpuBackend` runs batches through the C ABI.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, Deque, Dict, List, Optional, Sequence, Tuple
+
+
+@dataclasses.dataclass
+class Request:
+    """One frame to encrypt (kind "enc") or decrypt (kind "dec")."""
+    stream: int
+    seq: int
+    kind: str
+    frame: object                 # device uint8 (h, w, 3)
+    out: object                   # device uint8 (h, w, 3), written by the batch
+    hashes: object = None         # device uint8 (32,): output for "enc", input for "dec"
+    nbytes: int = 0               # device footprint while in flight
+    arrival: float = 0.0          # host time the request became available
+    launched: float = float("nan")
+    done: float = float("nan")
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+class Scheduler:
+    """Admission, ordering and batching.  ``launch(kind, requests)`` starts
+    a batch and returns a handle with ``query() -> bool`` (True once the
+    batch has completed)."""
+
+    def __init__(self, launch: Callable[[str, List[Request]], object], hbm_budget: int, max_inflight: int = 2,
+                 max_batch: int = 512, clock: Callable[[], float] = time.perf_counter,
+                 batch_class: Optional[Callable[[Request], object]] = None):
+        self.launch = launch
+        # Requests of different classes (e.g. resolutions) never share a
+        # batch, so a batch's completion is not held back by slower frames.
+        self.batch_class = batch_class
+        self.hbm_budget = hbm_budget
+        self.max_inflight = max_inflight
+        self.max_batch = max_batch
+        self.clock = clock
+        self.pending: Dict[str, Deque[Request]] = {"enc": collections.deque(), "dec": collections.deque()}
+        self.inflight: List[Tuple[str, object, List[Request]]] = []
+        self.inflight_bytes = 0
+        self.next_seq: Dict[Tuple[str, int], int] = collections.defaultdict(int)  # next seq to launch
+        self.completed: List[Request] = []
+        self.batches: List[Tuple[str, int]] = []  # (kind, size) of every launched batch
+
+    def submit(self, req: Request) -> None:
+        self.pending[req.kind].append(req)
+
+    def _inflight_of(self, kind: str) -> int:
+        return sum(1 for k, _, _ in self.inflight if k == kind)
+
+    def retire(self) -> int:
+        """Record completion of finished batches; returns how many retired."""
+        keep, n = [], 0
+        for kind, handle, reqs in self.inflight:
+            if handle.query():
+                t = self.clock()
+                for r in reqs:
+                    r.done = t
+                    self.inflight_bytes -= r.nbytes
+                self.completed.extend(reqs)
+                n += 1
+            else:
+                keep.append((kind, handle, reqs))
+        self.inflight = keep
+        return n
+
+    def _form_batch(self, kind: str) -> List[Request]:
+        """Requests to launch now, in arrival order: each the next frame of its
+        stream (counting frames taken earlier in this batch), within the
+        memory budget.  Passes over the queue repeat while they take
+        something, so a frame that arrived before its predecessor goes in
+        the same batch as it."""
+        q = self.pending[kind]
+        batch: List[Request] = []
+        cls = None
+        expect: Dict[Tuple[str, int], int] = {}
+        budget = self.hbm_budget - self.inflight_bytes
+        full = False
+        rest = list(q)
+        progress = True
+        while progress and not full:
+            progress = False
+            left: List[Request] = []
+            for i, r in enumerate(rest):
+                key = (kind, r.stream)
+                want = expect.get(key, self.next_seq[key])
+                rc = self.batch_class(r) if self.batch_class else None
+                if full or r.seq != want or (batch and rc != cls):
+                    left.append(r)
+                    continue
+                alone = not batch and not self.inflight
+                if r.nbytes > budget and not alone:
+                    full = True     # admission stops at the first request that does not fit
+                    left.append(r)
+                    continue
+                batch.append(r)
+                cls = rc
+                budget -= r.nbytes
+                expect[key] = want + 1
+                progress = True
+                if len(batch) >= self.max_batch:
+                    full = True
+            rest = left
+        q.clear()
+        q.extend(rest)
+        return batch
+
+    def pump(self) -> int:
+        """Retire finished batches and launch new ones while slots are free.
+        Returns the number of batches launched."""
+        self.retire()
+        launched = 0
+        for kind in ("enc", "dec"):
+            while self._inflight_of(kind) < self.max_inflight and self.pending[kind]:
+                batch = self._form_batch(kind)
+                if not batch:
+                    break
+                t = self.clock()
+                for r in batch:
+                    r.launched = t
+                    self.inflight_bytes += r.nbytes
+                    self.next_seq[(kind, r.stream)] = r.seq + 1
+                handle = self.launch(kind, batch)
+                self.inflight.append((kind, handle, batch))
+                self.batches.append((kind, len(batch)))
+                launched += 1
+        return launched
+
+    def idle(self) -> bool:
+        return not self.inflight and not any(self.pending.values())
+
+
+class GpuBackend:
+    """Runs batches through the library: a sender context for encrypt
+    requests and a receiver context for decrypt requests, each with two
+    alternating device streams."""
+
+    def __init__(self, key32: bytes, gamma: float, n: int, max_streams: int, scratch_bytes: int,
+                 overlap: Optional[Tuple[int, int, int]] = None, device_streams: int = 2):
+        import torch
+
+        from . import vcipher as V
+        self.torch = torch
+        self.V = V
+        self.ctx = {"enc": V.Cipher.from_bytes(key32, gamma, n, max_streams=max_streams, scratch_bytes=scratch_bytes),
+                    "dec": V.Cipher.from_bytes(key32, gamma, n, max_streams=max_streams, scratch_bytes=scratch_bytes)}
+        if overlap:
+            for c in self.ctx.values():
+                c.overlap(*overlap)
+        self.streams = {k: [torch.cuda.Stream() for _ in range(device_streams)] for k in ("enc", "dec")}
+        self.turn = {"enc": 0, "dec": 0}
+
+    def footprint(self, w: int, h: int) -> int:
+        """Device bytes a request holds while in flight: input, output and scratch."""
+        return 2 * 3 * w * h + self.V.vc_scratch_per_frame(w, h, self.ctx["enc"].n)
+
+    def launch(self, kind: str, reqs: Sequence[Request]):
+        torch, V = self.torch, self.V
+        st = self.streams[kind][self.turn[kind]]
+        self.turn[kind] = (self.turn[kind] + 1) % len(self.streams[kind])
+        c = self.ctx[kind]
+        frames = [r.frame for r in reqs]
+        outs = [r.out for r in reqs]
+        streams = [r.stream for r in reqs]
+        seqs = [r.seq for r in reqs]
+        hashes = torch.empty((len(reqs), 32), dtype=torch.uint8, device=frames[0].device)
+        with torch.cuda.stream(st):
+            if kind == "dec":
+                for i, r in enumerate(reqs):
+                    hashes[i].copy_(r.hashes)
+                V.decrypt_frames(c.ctx, frames, streams, seqs, hashes, outs, st)
+            else:
+                V.encrypt_frames(c.ctx, frames, streams, seqs, hashes, outs, st)
+                for i, r in enumerate(reqs):
+                    if r.hashes is not None:
+                        r.hashes.copy_(hashes[i])
+            ev = torch.cuda.Event()
+            ev.record(st)
+        hashes.record_stream(st)
+        return ev
+
+    def close(self) -> None:
+        for c in self.ctx.values():
+            c.close()

@@ -69,6 +69,8 @@ def _load() -> C.CDLL:
     L.vc_set_tuning.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_int]
     L.vc_set_overlap.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_uint32]
     L.vc_set_confusion_passes.argtypes = [vp, C.c_uint32]
+    L.vc_autotune.argtypes = [vp, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32),
+                              C.POINTER(C.c_uint32)]
     L.vc_scratch_per_frame.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
     L.vc_scratch_per_frame.restype = C.c_size_t
     L.vc_debug_confuse.argtypes = [vp, C.c_int, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape),
@@ -79,7 +81,7 @@ def _load() -> C.CDLL:
                  "cipher_stream_reset",
                  "cipher_stream_get_state", "cipher_stream_set_state", "cipher_status",
                  "vc_profile_enable", "vc_profile_read", "vc_profile_reset", "vc_set_tuning",
-                 "vc_set_overlap", "vc_set_confusion_passes",
+                 "vc_set_overlap", "vc_set_confusion_passes", "vc_autotune",
                  "vc_debug_confuse", "vc_debug_keysched", "vc_key_from_bytes"):
         getattr(L, name).restype = C.c_int
     return L
@@ -285,6 +287,13 @@ def vc_set_confusion_passes(ctx: int, passes: int = 2) -> None:
     _check(lib.vc_set_confusion_passes(C.c_void_p(ctx), passes), "vc_set_confusion_passes")
 
 
+def vc_autotune(ctx: int, decrypt: bool, w: int, h: int, frames: int) -> Tuple[int, int]:
+    strip, threads = C.c_uint32(0), C.c_uint32(0)
+    _check(lib.vc_autotune(C.c_void_p(ctx), 1 if decrypt else 0, w, h, frames, C.byref(strip), C.byref(threads)),
+           "vc_autotune")
+    return strip.value, threads.value
+
+
 def vc_scratch_per_frame(w: int, h: int, n: int) -> int:
     return int(lib.vc_scratch_per_frame(w, h, n))
 
@@ -432,3 +441,7 @@ class Cipher:
 
     def passes(self, passes: int = 2) -> None:
         vc_set_confusion_passes(self.ctx, passes)
+
+    def autotune(self, w: int, h: int, frames: int = 16, decrypt: bool = False) -> Tuple[int, int]:
+        """Tune the confusion tiling for w x h frames; returns (strip, threads)."""
+        return vc_autotune(self.ctx, decrypt, w, h, frames)

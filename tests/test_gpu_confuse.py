@@ -84,3 +84,19 @@ def test_mixed_shapes_and_unaligned_pointers(ctx):
     V.vc_debug_confuse(ctx.ctx, False, ins, Ds, Bs, outs)
     for P, D, B, C in zip(Ps, Ds, Bs, outs):
         assert np.array_equal(to_np(C), oracle.confuse_enc(P, to_np(D), to_np(B)))
+
+
+def test_autotuned_tiling_gives_the_same_bytes(ctx):
+    """The autotuner picks a tiling for a shape (timed on its own buffers);
+    calls on that shape then use it, with unchanged output."""
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(4242)
+    h, w = 90, 124
+    for decrypt in (False, True):
+        strip, threads = ctx.autotune(w, h, frames=4, decrypt=decrypt)
+        assert strip in (4, 8, 16, 32, 64) and threads in (256, 512, 1024)
+    P, D, B = case(rng, h, w)
+    (C,) = ctx.confuse([to_dev(P, dev)], [to_dev(D, dev)], [to_dev(B, dev)])
+    assert np.array_equal(to_np(C), oracle.confuse_enc(P, D, B))
+    (Q,) = ctx.confuse([C], [to_dev(D, dev)], [to_dev(B, dev)], decrypt=True)
+    assert np.array_equal(to_np(Q), P)

@@ -1,0 +1,75 @@
+"""The continuous-batching loop on the GPU: each stream's result is the same
+alone and in the mix (mixed resolutions, encrypt and decrypt requests,
+out-of-order arrivals, batches of several streams in flight at once)."""
+import random
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_util import require_gpu, to_dev, to_np
+from workload.synth import SynthVideo, key_bytes
+
+pytestmark = pytest.mark.gpu
+
+
+def test_results_alone_equal_results_in_the_mix():
+    dev = require_gpu()
+    from paper_2505_07158_amd import vcipher as V
+    from paper_2505_07158_amd.serving import GpuBackend, Request, Scheduler
+
+    kb, gamma, n, T = key_bytes(21), -1.0, 8, 5
+    enc_shapes = [(48, 64), (64, 96), (96, 128), (48, 64)]   # (h, w)
+    dec_shapes = [(64, 96), (32, 40)]
+    vids = {("enc", s): SynthVideo(w, h, seed=2100 + s).frames(T) for s, (h, w) in enumerate(enc_shapes)}
+    vids.update({("dec", s): SynthVideo(w, h, seed=2200 + s).frames(T) for s, (h, w) in enumerate(dec_shapes)})
+
+    # alone: every encrypt stream on a fresh context of its own
+    alone = {}
+    for s in range(len(enc_shapes)):
+        c = V.Cipher.from_bytes(kb, gamma, n)
+        C, H = c.encrypt(to_dev(vids[("enc", s)], dev))
+        alone[s] = (to_np(C), to_np(H))
+        c.close()
+    # ciphertext for the decrypt streams from a separate sender context
+    sender = V.Cipher.from_bytes(kb, gamma, n, max_streams=len(dec_shapes))
+    dec_in = {}
+    for s in range(len(dec_shapes)):
+        C, H = sender.encrypt(to_dev(vids[("dec", s)], dev), streams=[s] * T)
+        dec_in[s] = (C, H)
+    sender.close()
+    torch.cuda.synchronize()
+
+    be = GpuBackend(kb, gamma, n, max_streams=8, scratch_bytes=64 << 20)
+    sched = Scheduler(be.launch, hbm_budget=1 << 30, max_inflight=2, max_batch=5)
+    reqs = []
+    for (kind, s), v in vids.items():
+        for t in range(T):
+            if kind == "enc":
+                frame = to_dev(v[t], dev)
+                hashes = torch.empty(32, dtype=torch.uint8, device=dev)
+            else:
+                frame = dec_in[s][0][t]
+                hashes = dec_in[s][1][t]
+            reqs.append(Request(stream=s, seq=t, kind=kind, frame=frame, out=torch.empty_like(frame), hashes=hashes,
+                                nbytes=be.footprint(frame.shape[1], frame.shape[0])))
+    order = list(reqs)
+    random.Random(5).shuffle(order)     # arrivals out of order, also within a stream
+    torch.cuda.synchronize()
+    for r in order:
+        sched.submit(r)
+        sched.pump()
+    while not sched.idle():
+        sched.pump()
+    torch.cuda.synchronize()
+    assert len(sched.completed) == len(reqs)
+    assert any(k == "enc" and size > 1 for k, size in sched.batches), sched.batches
+    for r in reqs:
+        if r.kind == "enc":
+            C, H = alone[r.stream]
+            assert np.array_equal(to_np(r.out), C[r.seq]), (r.stream, r.seq)
+            assert to_np(r.hashes).tobytes() == H[r.seq].tobytes()
+        else:
+            assert np.array_equal(to_np(r.out), vids[("dec", r.stream)][r.seq]), (r.stream, r.seq)
+    assert be.ctx["enc"].status() == 0 and be.ctx["dec"].status() == 0
+    be.close()

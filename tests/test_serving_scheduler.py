@@ -1,0 +1,147 @@
+"""The serving loop's scheduling rules on the CPU (no device): admission by
+memory budget, per-stream order, in-flight limits, continuous batching."""
+import random
+
+import pytest
+
+from paper_2505_07158_amd.serving import Request, Scheduler
+
+
+class FakeHandle:
+    def __init__(self):
+        self.finished = False
+
+    def query(self):
+        return self.finished
+
+
+class FakeBackend:
+    def __init__(self):
+        self.launched = []   # (kind, [(stream, seq)], handle)
+
+    def launch(self, kind, reqs):
+        h = FakeHandle()
+        self.launched.append((kind, [(r.stream, r.seq) for r in reqs], h))
+        return h
+
+    def finish_all(self):
+        for _, _, h in self.launched:
+            h.finished = True
+
+
+def req(stream, seq, kind="enc", nbytes=10, arrival=0.0):
+    return Request(stream=stream, seq=seq, kind=kind, frame=None, out=None, nbytes=nbytes, arrival=arrival)
+
+
+def test_frames_of_a_stream_launch_in_order():
+    be = FakeBackend()
+    s = Scheduler(be.launch, hbm_budget=1000)
+    s.submit(req(0, 1))          # frame 1 arrives before frame 0
+    s.submit(req(1, 0))
+    s.pump()
+    assert be.launched[0][1] == [(1, 0)]          # stream 0 waits for its frame 0
+    s.submit(req(0, 0))
+    be.finish_all()
+    s.pump()
+    assert be.launched[1][1] == [(0, 0), (0, 1)]  # then both, in sequence order
+    be.finish_all()
+    s.pump()
+    assert s.idle() and len(s.completed) == 3
+
+
+def test_budget_limits_in_flight_bytes():
+    be = FakeBackend()
+    s = Scheduler(be.launch, hbm_budget=100, max_inflight=4)
+    for k in range(10):
+        s.submit(req(k, 0, nbytes=30))
+    s.pump()
+    # 3 requests fit in the first batch; nothing else fits while it is in flight
+    assert [len(b) for _, b, _ in be.launched] == [3]
+    assert s.inflight_bytes == 90
+    be.finish_all()
+    s.pump()
+    assert [len(b) for _, b, _ in be.launched] == [3, 3]
+
+
+def test_oversized_request_runs_alone():
+    be = FakeBackend()
+    s = Scheduler(be.launch, hbm_budget=100)
+    s.submit(req(0, 0, nbytes=500))
+    s.submit(req(1, 0, nbytes=10))
+    s.pump()
+    assert be.launched[0][1] == [(0, 0)]
+    assert len(be.launched) == 1     # the small one waits: the big one holds more than the budget
+    be.finish_all()
+    s.pump()
+    assert be.launched[1][1] == [(1, 0)]
+
+
+def test_inflight_limit_and_continuous_admission():
+    be = FakeBackend()
+    s = Scheduler(be.launch, hbm_budget=10**9, max_inflight=2)
+    s.submit(req(0, 0))
+    s.pump()
+    s.submit(req(1, 0))
+    s.pump()
+    s.submit(req(2, 0))
+    s.pump()
+    assert len(be.launched) == 2                   # two batches in flight, the third request waits
+    be.launched[0][2].finished = True
+    s.pump()                                       # a slot frees: the waiting request is admitted
+    assert len(be.launched) == 3 and be.launched[2][1] == [(2, 0)]
+
+
+def test_encrypt_and_decrypt_are_independent_kinds():
+    be = FakeBackend()
+    s = Scheduler(be.launch, hbm_budget=10**9, max_inflight=1)
+    s.submit(req(0, 0, "enc"))
+    s.submit(req(0, 0, "dec"))     # same stream id, other context: its own sequence
+    s.pump()
+    assert sorted(k for k, _, _ in be.launched) == ["dec", "enc"]
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_random_arrivals_all_complete_in_order(seed):
+    rng = random.Random(seed)
+    be = FakeBackend()
+    s = Scheduler(be.launch, hbm_budget=200, max_inflight=2, max_batch=7)
+    reqs = [req(st, q, rng.choice(["enc", "dec"]) if st % 2 else "enc", nbytes=rng.randint(1, 60))
+            for st in range(6) for q in range(12)]
+    # per stream (and kind) sequence numbers must be dense: renumber per (kind, stream)
+    nxt = {}
+    for r in reqs:
+        r.seq = nxt.get((r.kind, r.stream), 0)
+        nxt[(r.kind, r.stream)] = r.seq + 1
+    order = list(reqs)
+    rng.shuffle(order)
+    for r in order:
+        s.submit(r)
+        s.pump()
+        if rng.random() < 0.5:
+            for _, _, h in be.launched:
+                if rng.random() < 0.5:
+                    h.finished = True
+        assert s.inflight_bytes <= 200 or len(s.inflight) == 1
+    while not s.idle():
+        be.finish_all()
+        s.pump()
+    assert len(s.completed) == len(reqs)
+    launched_seq = {}
+    for kind, items, _ in be.launched:
+        for st, q in items:
+            assert q == launched_seq.get((kind, st), 0)
+            launched_seq[(kind, st)] = q + 1
+
+
+def test_batch_class_keeps_batches_homogeneous():
+    be = FakeBackend()
+    cls = {0: "small", 1: "big", 2: "small", 3: "big"}
+    s = Scheduler(be.launch, hbm_budget=10**9, max_inflight=8, batch_class=lambda r: cls[r.stream])
+    for q in range(3):
+        for st in range(4):
+            s.submit(req(st, q))
+    s.pump()
+    assert len(be.launched) == 2
+    for _, items, _ in be.launched:
+        assert len({cls[st] for st, _ in items}) == 1
+    assert sorted(len(items) for _, items, _ in be.launched) == [6, 6]
