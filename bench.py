@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--hbm-budget-gb", type=float, default=16.0, help="serving: admission budget")
     ap.add_argument("--max-batch", type=int, default=256, help="serving: frames per batch at most")
     ap.add_argument("--plain-frames", type=int, default=400, help="serving: arrivals replayed one frame per launch")
-    ap.add_argument("--inflight", type=int, default=3, help="serving: batches of a kind in flight (device streams)")
+    ap.add_argument("--inflight", type=int, default=2, help="serving: batches in flight per kind and resolution")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=32, help="worker count (key material)")
@@ -170,8 +170,11 @@ def run_serving(args) -> None:
     budget = int(args.hbm_budget_gb * (1 << 30))
 
     def one_run(trace, max_batch, max_inflight):
-        be = GpuBackend(kb, gamma, n, max_streams=S, scratch_bytes=budget, overlap=(args.parts, args.side, 2),
-                        device_streams=max_inflight)
+        cls = (lambda r: (streams[r.stream]["w"], streams[r.stream]["h"]))
+        # one context pair per resolution, each with its chain stream and one
+        # side stream, and 2 device streams per (kind, resolution)
+        be = GpuBackend(kb, gamma, n, max_streams=S, scratch_bytes=max(budget // len(res_set), 1 << 30),
+                        overlap=(2, 1, 2), device_streams=2, classes=res_set, batch_class=cls)
         dec_src = {}
         sender = V.Cipher.from_bytes(kb, gamma, n, max_streams=S, scratch_bytes=max(budget // 4, 1 << 30))
         for s, st in enumerate(streams):
@@ -181,7 +184,7 @@ def run_serving(args) -> None:
         torch.cuda.synchronize()
         sender.close()
         sched = Scheduler(be.launch, hbm_budget=budget, max_inflight=max_inflight, max_batch=max_batch,
-                          batch_class=lambda r: (streams[r.stream]["w"], streams[r.stream]["h"]))
+                          batch_class=cls)
         reqs = []
         i = 0
         t0 = time.perf_counter()
@@ -205,7 +208,7 @@ def run_serving(args) -> None:
         wall = time.perf_counter() - t0
         # decrypt requests whose ciphertext matches their sequence number
         ok = all(torch.equal(r.out, pool[r.stream][r.seq]) for r in reqs if r.kind == "dec" and r.seq < P)
-        status_ok = be.ctx["enc"].status() == 0 and be.ctx["dec"].status() == 0
+        status_ok = be.status_ok()
         be.close()
         lat = np.array([1000.0 * r.latency for r in reqs])
         late = np.array([1000.0 * r.latency > 1000.0 / streams[r.stream]["fps"] for r in reqs])
@@ -234,7 +237,7 @@ def run_serving(args) -> None:
                                    "640x480/1280x720/1920x1080/3840x2160, 30% decrypt streams, "
                                    f"{args.duration} s trace", "n": n, "offered_frames_per_s": round(offered, 1),
                        "hbm_budget_gb": args.hbm_budget_gb, "max_batch": args.max_batch,
-                       "inflight_batches_per_kind": args.inflight, "batch_class": "resolution"},
+                       "inflight_batches_per_kind_and_resolution": args.inflight, "batch_class": "resolution"},
             "continuous_batching": batched, "plain_per_frame": plain}
     print(json.dumps(line), flush=True)
 
@@ -340,6 +343,8 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path (streams would shard "
               "across GPUs with no collective; see the design notes).  Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "serving" and args.hw_queues == 16:
+        args.hw_queues = 32     # 8 contexts x 2 streams + 16 device streams + the null stream
     if args.hw_queues:
         if not 1 <= args.hw_queues <= 32:
             sys.exit("--hw-queues must be in 1..32")

@@ -280,15 +280,50 @@ __global__ __launch_bounds__(128) void lhcs_keygen(const FrameDesc *__restrict__
     bool ok = true;
     uint32_t carry = 0;  // word 5 of the previous step
 
+    // Steps [fast_lo, fast_core) need no bytewise work at all; the last fast
+    // step also stores its final phi bytes bytewise.
+    const uint64_t fast_core = (phi && fast_hi > fast_lo) ? fast_hi - 1 : fast_hi;
+
     for (uint32_t blk = 0; blk < nblk; ++blk) {
         __syncthreads();
         if (!live) continue;
+        const uint64_t s0 = static_cast<uint64_t>(blk) * kKgHalf;
+        const V4 *half = &ring[(blk & 1) * kKgHalf][0];
+        if (s0 >= fast_lo && s0 + kKgHalf <= fast_core) {
+            // a whole half of the ring in the keystream region: dword stores only
+            VC_GLOBAL uint8_t *dst = Bw + (24 * s0 - two_nd - phi) + (odd ? 12 : 0);
+#pragma unroll
+            for (uint32_t j = 0; j < kKgHalf; ++j) {
+                const V4 a = half[64 * j + (lane & ~1u)];
+                const V4 b = half[64 * j + (lane | 1u)];
+                const uint64_t u0 = bits(a.x) ^ bits(b.x), u1 = bits(a.y) ^ bits(b.y);
+                const uint64_t u2 = bits(a.z) ^ bits(b.z), u3 = bits(a.w) ^ bits(b.w);
+                const uint32_t w0 = static_cast<uint32_t>(u0);
+                const uint32_t w1 = static_cast<uint32_t>((u0 >> 32) & 0xFFFF) | (static_cast<uint32_t>(u1) << 16);
+                const uint32_t w2 = static_cast<uint32_t>(u1 >> 16);
+                const uint32_t w3 = static_cast<uint32_t>(u2);
+                const uint32_t w4 = static_cast<uint32_t>((u2 >> 32) & 0xFFFF) | (static_cast<uint32_t>(u3) << 16);
+                const uint32_t w5 = static_cast<uint32_t>(u3 >> 16);
+                const uint32_t p0 = odd ? w2 : carry;
+                const uint32_t p1 = odd ? w3 : w0;
+                const uint32_t p2 = odd ? w4 : w1;
+                const uint32_t p3 = odd ? w5 : w2;
+                u32x3_a4 v;
+                v.x = static_cast<uint32_t>(((static_cast<uint64_t>(p1) << 32) | p0) >> shr);
+                v.y = static_cast<uint32_t>(((static_cast<uint64_t>(p2) << 32) | p1) >> shr);
+                v.z = static_cast<uint32_t>(((static_cast<uint64_t>(p3) << 32) | p2) >> shr);
+                *reinterpret_cast<VC_GLOBAL u32x3_a4 *>(dst) = v;
+                dst += 24;
+                carry = w5;
+            }
+            continue;
+        }
 #pragma unroll 1
         for (uint32_t j = 0; j < kKgHalf; ++j) {
-            const uint64_t s = static_cast<uint64_t>(blk) * kKgHalf + j;
+            const uint64_t s = s0 + j;
             if (s >= steps) break;
-            const V4 a = ring[(blk & 1) * kKgHalf + j][lane & ~1u];
-            const V4 b = ring[(blk & 1) * kKgHalf + j][lane | 1u];
+            const V4 a = half[64 * j + (lane & ~1u)];
+            const V4 b = half[64 * j + (lane | 1u)];
             const uint64_t u0 = bits(a.x) ^ bits(b.x), u1 = bits(a.y) ^ bits(b.y);
             const uint64_t u2 = bits(a.z) ^ bits(b.z), u3 = bits(a.w) ^ bits(b.w);
             uint32_t w[6];

@@ -55,7 +55,8 @@ class Request:
 class Scheduler:
     """Admission, ordering and batching.  ``launch(kind, requests)`` starts
     a batch and returns a handle with ``query() -> bool`` (True once the
-    batch has completed)."""
+    batch has completed).  At most ``max_inflight`` batches of a kind (of a
+    kind and class, with ``batch_class``) are in flight."""
 
     def __init__(self, launch: Callable[[str, List[Request]], object], hbm_budget: int, max_inflight: int = 2,
                  max_batch: int = 512, clock: Callable[[], float] = time.perf_counter,
@@ -78,8 +79,12 @@ class Scheduler:
     def submit(self, req: Request) -> None:
         self.pending[req.kind].append(req)
 
-    def _inflight_of(self, kind: str) -> int:
-        return sum(1 for k, _, _ in self.inflight if k == kind)
+    def _class_of(self, r: Request):
+        return self.batch_class(r) if self.batch_class else None
+
+    def _inflight_of(self, kind: str, cls=None) -> int:
+        """Batches of a kind (and class, with batch classes) on the GPU."""
+        return sum(1 for k, _, reqs in self.inflight if k == kind and self._class_of(reqs[0]) == cls)
 
     def retire(self) -> int:
         """Record completion of finished batches; returns how many retired."""
@@ -117,8 +122,9 @@ class Scheduler:
             for i, r in enumerate(rest):
                 key = (kind, r.stream)
                 want = expect.get(key, self.next_seq[key])
-                rc = self.batch_class(r) if self.batch_class else None
-                if full or r.seq != want or (batch and rc != cls):
+                rc = self._class_of(r)
+                if full or r.seq != want or (batch and rc != cls) or \
+                        (not batch and self._inflight_of(kind, rc) >= self.max_inflight):
                     left.append(r)
                     continue
                 alone = not batch and not self.inflight
@@ -144,7 +150,7 @@ class Scheduler:
         self.retire()
         launched = 0
         for kind in ("enc", "dec"):
-            while self._inflight_of(kind) < self.max_inflight and self.pending[kind]:
+            while self.pending[kind]:
                 batch = self._form_batch(kind)
                 if not batch:
                     break
@@ -164,34 +170,50 @@ class Scheduler:
 
 
 class GpuBackend:
-    """Runs batches through the library: a sender context for encrypt
-    requests and a receiver context for decrypt requests, each with two
-    alternating device streams."""
+    """Runs batches through the library.  Encrypt requests go to sender
+    contexts and decrypt requests to receiver contexts; with
+    ``batch_class`` there is one context pair per class (each stream's frames
+    always fall in one class, so each chain lives in one context), so that
+    batches of different classes never queue behind each other on a
+    context's streams.  Each (kind, class) rotates over ``device_streams``
+    device streams."""
 
     def __init__(self, key32: bytes, gamma: float, n: int, max_streams: int, scratch_bytes: int,
-                 overlap: Optional[Tuple[int, int, int]] = None, device_streams: int = 2):
+                 overlap: Optional[Tuple[int, int, int]] = None, device_streams: int = 2,
+                 classes: Optional[Sequence[object]] = None,
+                 batch_class: Optional[Callable[[Request], object]] = None):
         import torch
 
         from . import vcipher as V
         self.torch = torch
         self.V = V
-        self.ctx = {"enc": V.Cipher.from_bytes(key32, gamma, n, max_streams=max_streams, scratch_bytes=scratch_bytes),
-                    "dec": V.Cipher.from_bytes(key32, gamma, n, max_streams=max_streams, scratch_bytes=scratch_bytes)}
-        if overlap:
-            for c in self.ctx.values():
-                c.overlap(*overlap)
-        self.streams = {k: [torch.cuda.Stream() for _ in range(device_streams)] for k in ("enc", "dec")}
-        self.turn = {"enc": 0, "dec": 0}
+        self.n = n
+        self.batch_class = batch_class
+        self.ctx: Dict[Tuple[str, object], object] = {}
+        self.streams: Dict[Tuple[str, object], list] = {}
+        self.turn: Dict[Tuple[str, object], int] = {}
+        for cls in (classes if classes else [None]):
+            for kind in ("enc", "dec"):
+                c = V.Cipher.from_bytes(key32, gamma, n, max_streams=max_streams, scratch_bytes=scratch_bytes)
+                if overlap:
+                    c.overlap(*overlap)
+                self.ctx[(kind, cls)] = c
+                self.streams[(kind, cls)] = [torch.cuda.Stream() for _ in range(device_streams)]
+                self.turn[(kind, cls)] = 0
 
     def footprint(self, w: int, h: int) -> int:
         """Device bytes a request holds while in flight: input, output and scratch."""
-        return 2 * 3 * w * h + self.V.vc_scratch_per_frame(w, h, self.ctx["enc"].n)
+        return 2 * 3 * w * h + self.V.vc_scratch_per_frame(w, h, self.n)
+
+    def status_ok(self) -> bool:
+        return all(c.status() == 0 for c in self.ctx.values())
 
     def launch(self, kind: str, reqs: Sequence[Request]):
         torch, V = self.torch, self.V
-        st = self.streams[kind][self.turn[kind]]
-        self.turn[kind] = (self.turn[kind] + 1) % len(self.streams[kind])
-        c = self.ctx[kind]
+        key = (kind, self.batch_class(reqs[0]) if self.batch_class else None)
+        st = self.streams[key][self.turn[key]]
+        self.turn[key] = (self.turn[key] + 1) % len(self.streams[key])
+        c = self.ctx[key]
         frames = [r.frame for r in reqs]
         outs = [r.out for r in reqs]
         streams = [r.stream for r in reqs]

@@ -13,7 +13,8 @@ from workload.synth import SynthVideo, key_bytes
 pytestmark = pytest.mark.gpu
 
 
-def test_results_alone_equal_results_in_the_mix():
+@pytest.mark.parametrize("per_class", [False, True])
+def test_results_alone_equal_results_in_the_mix(per_class):
     dev = require_gpu()
     from paper_2505_07158_amd import vcipher as V
     from paper_2505_07158_amd.serving import GpuBackend, Request, Scheduler
@@ -40,8 +41,12 @@ def test_results_alone_equal_results_in_the_mix():
     sender.close()
     torch.cuda.synchronize()
 
-    be = GpuBackend(kb, gamma, n, max_streams=8, scratch_bytes=64 << 20)
-    sched = Scheduler(be.launch, hbm_budget=1 << 30, max_inflight=2, max_batch=5)
+    shape_of = {("enc", s): sh for s, sh in enumerate(enc_shapes)}
+    shape_of.update({("dec", s): sh for s, sh in enumerate(dec_shapes)})
+    cls = (lambda r: shape_of[(r.kind, r.stream)]) if per_class else None
+    be = GpuBackend(kb, gamma, n, max_streams=8, scratch_bytes=64 << 20, batch_class=cls,
+                    classes=sorted(set(shape_of.values())) if per_class else None)
+    sched = Scheduler(be.launch, hbm_budget=1 << 30, max_inflight=2, max_batch=5, batch_class=cls)
     reqs = []
     for (kind, s), v in vids.items():
         for t in range(T):
@@ -71,5 +76,5 @@ def test_results_alone_equal_results_in_the_mix():
             assert to_np(r.hashes).tobytes() == H[r.seq].tobytes()
         else:
             assert np.array_equal(to_np(r.out), vids[("dec", r.stream)][r.seq]), (r.stream, r.seq)
-    assert be.ctx["enc"].status() == 0 and be.ctx["dec"].status() == 0
+    assert be.status_ok()
     be.close()
