@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--max-batch", type=int, default=256, help="serving: frames per batch at most")
     ap.add_argument("--plain-frames", type=int, default=400, help="serving: arrivals replayed one frame per launch")
     ap.add_argument("--inflight", type=int, default=2, help="serving: batches in flight per kind and resolution")
+    ap.add_argument("--serve-parts", type=int, default=1, help="serving: parts per call (vc_set_overlap)")
+    ap.add_argument("--serve-side", type=int, default=1, help="serving: side streams per context (vc_set_overlap)")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=32, help="worker count (key material)")
@@ -171,10 +173,12 @@ def run_serving(args) -> None:
 
     def one_run(trace, max_batch, max_inflight):
         cls = (lambda r: (streams[r.stream]["w"], streams[r.stream]["h"]))
-        # one context pair per resolution, each with its chain stream and one
-        # side stream, and 2 device streams per (kind, resolution)
+        # one context pair per resolution, each with its chain stream and
+        # --serve-side side streams, and one device stream per in-flight batch
+        # of each (kind, resolution)
         be = GpuBackend(kb, gamma, n, max_streams=S, scratch_bytes=max(budget // len(res_set), 1 << 30),
-                        overlap=(2, 1, 2), device_streams=2, classes=res_set, batch_class=cls)
+                        overlap=(args.serve_parts, args.serve_side, 2), device_streams=max(max_inflight, 1),
+                        classes=res_set, batch_class=cls)
         dec_src = {}
         sender = V.Cipher.from_bytes(kb, gamma, n, max_streams=S, scratch_bytes=max(budget // 4, 1 << 30))
         for s, st in enumerate(streams):
@@ -209,6 +213,7 @@ def run_serving(args) -> None:
         # decrypt requests whose ciphertext matches their sequence number
         ok = all(torch.equal(r.out, pool[r.stream][r.seq]) for r in reqs if r.kind == "dec" and r.seq < P)
         status_ok = be.status_ok()
+        host_launch_s = be.launch_seconds
         be.close()
         lat = np.array([1000.0 * r.latency for r in reqs])
         late = np.array([1000.0 * r.latency > 1000.0 / streams[r.stream]["fps"] for r in reqs])
@@ -224,7 +229,8 @@ def run_serving(args) -> None:
                 "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
                 "delay_rate": round(float(late.mean()), 4), "per_resolution": per_res, "batches": len(sizes),
                 "mean_batch": round(float(np.mean(sizes)), 2), "max_batch_seen": int(max(sizes)),
-                "decrypt_check_ok": bool(ok), "status_ok": bool(status_ok)}
+                "decrypt_check_ok": bool(ok), "status_ok": bool(status_ok),
+                "host_ms_per_batch": round(1000.0 * host_launch_s / max(len(sizes), 1), 3)}
 
     batched = one_run(trace, args.max_batch, args.inflight)
     # The plain per-frame path cannot keep up with the offered load; it runs
@@ -237,7 +243,8 @@ def run_serving(args) -> None:
                                    "640x480/1280x720/1920x1080/3840x2160, 30% decrypt streams, "
                                    f"{args.duration} s trace", "n": n, "offered_frames_per_s": round(offered, 1),
                        "hbm_budget_gb": args.hbm_budget_gb, "max_batch": args.max_batch,
-                       "inflight_batches_per_kind_and_resolution": args.inflight, "batch_class": "resolution"},
+                       "inflight_batches_per_kind_and_resolution": args.inflight, "batch_class": "resolution",
+                       "parts": args.serve_parts, "side_streams": args.serve_side},
             "continuous_batching": batched, "plain_per_frame": plain}
     print(json.dumps(line), flush=True)
 

@@ -189,6 +189,7 @@ class GpuBackend:
         self.V = V
         self.n = n
         self.batch_class = batch_class
+        self.launch_seconds = 0.0   # host time spent enqueueing batches
         self.ctx: Dict[Tuple[str, object], object] = {}
         self.streams: Dict[Tuple[str, object], list] = {}
         self.turn: Dict[Tuple[str, object], int] = {}
@@ -209,6 +210,7 @@ class GpuBackend:
         return all(c.status() == 0 for c in self.ctx.values())
 
     def launch(self, kind: str, reqs: Sequence[Request]):
+        t0 = time.perf_counter()
         torch, V = self.torch, self.V
         key = (kind, self.batch_class(reqs[0]) if self.batch_class else None)
         st = self.streams[key][self.turn[key]]
@@ -232,6 +234,7 @@ class GpuBackend:
             ev = torch.cuda.Event()
             ev.record(st)
         hashes.record_stream(st)
+        self.launch_seconds += time.perf_counter() - t0
         return ev
 
     def close(self) -> None:
