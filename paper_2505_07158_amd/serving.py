@@ -60,8 +60,12 @@ class Scheduler:
 
     def __init__(self, launch: Callable[[str, List[Request]], object], hbm_budget: int, max_inflight: int = 2,
                  max_batch: int = 512, clock: Callable[[], float] = time.perf_counter,
-                 batch_class: Optional[Callable[[Request], object]] = None):
+                 batch_class: Optional[Callable[[Request], object]] = None, max_stream_inflight: int = 0):
         self.launch = launch
+        # at most this many frames of one stream in flight (0 = no limit), e.g.
+        # to bound a per-stream ring of output buffers
+        self.max_stream_inflight = max_stream_inflight
+        self.stream_inflight: Dict[Tuple[str, int], int] = collections.defaultdict(int)
         # Requests of different classes (e.g. resolutions) never share a
         # batch, so a batch's completion is not held back by slower frames.
         self.batch_class = batch_class
@@ -95,6 +99,7 @@ class Scheduler:
                 for r in reqs:
                     r.done = t
                     self.inflight_bytes -= r.nbytes
+                    self.stream_inflight[(kind, r.stream)] -= 1
                 self.completed.extend(reqs)
                 n += 1
             else:
@@ -123,8 +128,11 @@ class Scheduler:
                 key = (kind, r.stream)
                 want = expect.get(key, self.next_seq[key])
                 rc = self._class_of(r)
+                taken = want - self.next_seq[key]   # frames of this stream already in this batch
                 if full or r.seq != want or (batch and rc != cls) or \
-                        (not batch and self._inflight_of(kind, rc) >= self.max_inflight):
+                        (not batch and self._inflight_of(kind, rc) >= self.max_inflight) or \
+                        (self.max_stream_inflight and
+                         self.stream_inflight[key] + taken >= self.max_stream_inflight):
                     left.append(r)
                     continue
                 alone = not batch and not self.inflight
@@ -159,6 +167,7 @@ class Scheduler:
                     r.launched = t
                     self.inflight_bytes += r.nbytes
                     self.next_seq[(kind, r.stream)] = r.seq + 1
+                    self.stream_inflight[(kind, r.stream)] += 1
                 handle = self.launch(kind, batch)
                 self.inflight.append((kind, handle, batch))
                 self.batches.append((kind, len(batch)))

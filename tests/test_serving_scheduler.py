@@ -145,3 +145,15 @@ def test_batch_class_keeps_batches_homogeneous():
     for _, items, _ in be.launched:
         assert len({cls[st] for st, _ in items}) == 1
     assert sorted(len(items) for _, items, _ in be.launched) == [6, 6]
+
+
+def test_per_stream_inflight_limit():
+    be = FakeBackend()
+    s = Scheduler(be.launch, hbm_budget=10**9, max_inflight=8, max_stream_inflight=2)
+    for q in range(5):
+        s.submit(req(0, q))
+    s.pump()
+    assert [items for _, items, _ in be.launched] == [[(0, 0), (0, 1)]]
+    be.finish_all()
+    s.pump()
+    assert be.launched[1][1] == [(0, 2), (0, 3)]
