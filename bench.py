@@ -48,6 +48,8 @@ def parse():
     ap.add_argument("--max-batch", type=int, default=256, help="serving: frames per batch at most")
     ap.add_argument("--plain-frames", type=int, default=400, help="serving: arrivals replayed one frame per launch")
     ap.add_argument("--inflight", type=int, default=2, help="serving: batches in flight per kind and resolution")
+    ap.add_argument("--inflight-4k", type=int, default=0,
+                    help="serving: batches in flight per kind at 3840x2160 (0 = --inflight)")
     ap.add_argument("--serve-parts", type=int, default=1, help="serving: parts per call (vc_set_overlap)")
     ap.add_argument("--serve-side", type=int, default=0, help="serving: side streams per context (vc_set_overlap)")
     ap.add_argument("--steps", type=int, default=10)
@@ -71,6 +73,7 @@ def parse():
     ap.add_argument("--latency-iters", type=int, default=30)
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stats", action="store_true", help="skip the statistics of one ciphertext batch")
     ap.add_argument("--second-n", type=int, default=256, help="worker count of the second row (0 = skip)")
     ap.add_argument("--second-steps", type=int, default=3)
     ap.add_argument("--unpipelined-steps", type=int, default=4, help="steps of the reference without the pipeline")
@@ -179,11 +182,12 @@ def run_serving(args) -> None:
         # --serve-side side streams, and one device stream per in-flight batch
         # of each (kind, resolution)
         return cls, GpuBackend(kb, gamma, n, max_streams=S, scratch_bytes=max(budget // len(res_set), 1 << 30),
-                               overlap=(args.serve_parts, args.serve_side, 2), device_streams=max(max_inflight, 1),
+                               overlap=(args.serve_parts, args.serve_side, 2),
+                               device_streams=lambda kind, c: max(max_inflight(kind, c), 1),
                                classes=res_set, batch_class=cls)
 
     # warm-up: every kernel variant the trace uses is loaded and run once
-    _, wb = make_backend(1)
+    _, wb = make_backend(lambda kind, c: 1)
     for s, st in enumerate(streams):
         if all(streams[x]["w"] != st["w"] or streams[x]["h"] != st["h"] for x in range(s)):
             for kind in ("enc", "dec"):
@@ -253,10 +257,14 @@ def run_serving(args) -> None:
                 "decrypt_check_ok": bool(ok), "status_ok": bool(status_ok),
                 "host_ms_per_batch": round(1000.0 * host_launch_s / max(len(sizes), 1), 3)}
 
-    batched = one_run(trace, args.max_batch, args.inflight)
+    # in flight per kind and resolution: --inflight (--inflight-4k at 3840x2160)
+    # (at 2: 16 device streams + 8 chain streams, within 32 hardware queues)
+    infl4k = args.inflight_4k or args.inflight
+    infl = lambda kind, c: max(1, infl4k if c == (3840, 2160) else args.inflight)
+    batched = one_run(trace, args.max_batch, infl)
     # The plain per-frame path cannot keep up with the offered load; it runs
     # the first --plain-frames arrivals of the same trace.
-    plain = one_run(trace[:args.plain_frames], 1, 1)
+    plain = one_run(trace[:args.plain_frames], 1, lambda kind, c: 1)
     offered = len(trace) / args.duration
     line = {"metric": "serving: p50/p99 arrival-to-completion latency (ms), frames/s", "value": batched["p99_ms"],
             "unit": "ms (p99)", "n_gpus": 1, "higher_is_better": False, "dtype": "u8", "data": "synthetic",
@@ -264,7 +272,8 @@ def run_serving(args) -> None:
                                    "640x480/1280x720/1920x1080/3840x2160, 30% decrypt streams, "
                                    f"{args.duration} s trace", "n": n, "offered_frames_per_s": round(offered, 1),
                        "hbm_budget_gb": args.hbm_budget_gb, "max_batch": args.max_batch,
-                       "inflight_batches_per_kind_and_resolution": args.inflight, "batch_class": "resolution",
+                       "inflight_batches_per_kind_and_resolution": f"{args.inflight} ({infl4k} at 3840x2160)",
+                       "batch_class": "resolution",
                        "parts": args.serve_parts, "side_streams": args.serve_side},
             "continuous_batching": batched, "plain_per_frame": plain}
     print(json.dumps(line), flush=True)
@@ -693,6 +702,35 @@ def main():
             lat_e.append((b - a) * 1e3)
             lat_d.append((c - b) * 1e3)
 
+    # ---- statistics (histogram variance, chi-square, correlation, entropy,
+    # local entropy) of one ciphertext batch and of plaintext frames: counts
+    # reduced on the GPU, formulas on the host ----
+    statistics = None
+    if not args.no_stats:
+        from paper_2505_07158_amd import stats as S
+        cf = list(cbuf[0])
+        V.vc_frame_histograms(cf[:2])
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        V.vc_frame_histograms(cf)
+        t_hist = time.perf_counter() - a
+        a = time.perf_counter()
+        st_c = S.summarize(S.frame_statistics(cf, seed=0))
+        t_suite = time.perf_counter() - a
+        st_p = S.summarize(S.frame_statistics(list(frames[:16]), seed=0))
+
+        def r6(d):
+            return {k: (round(v, 6) if isinstance(v, float) else v) for k, v in d.items()}
+        statistics = {"ciphertext": r6(st_c), "plaintext": r6(st_p),
+                      "histogram_call_ms": round(1e3 * t_hist, 3),
+                      "histogram_call_GBps": round(T * L / t_hist / 1e9, 1),
+                      "suite_seconds": round(t_suite, 3),
+                      "note": f"ciphertext: {T} frames of one batch; plaintext: 16 frames; "
+                              f"{S.CORR_PAIRS} random pairs and {S.LSE_BLOCKS} blocks of {S.LSE_SIDE}x{S.LSE_SIDE} "
+                              "per frame; chi2_pass = fraction of channels under 293.25, lse_pass = fraction "
+                              "inside (7.901515798, 7.903422936); timings are host wall clock of synchronous "
+                              "calls"}
+
     # ---- CPU oracle on this host (bounded sample, same chain as step 1) ----
     cpu = None
     verified = None
@@ -749,6 +787,7 @@ def main():
                         "mode": f"one {w}x{h} frame per call, host-synchronised"} if lat_e else None),
         "second_row": second,
         "unpipelined": unpiped,
+        "statistics": statistics,
         "cpu_baseline": cpu,
         "roundtrip_ok": roundtrip_ok,
         "oracle_verified_sample": verified,

@@ -242,6 +242,38 @@ int vc_debug_keysched(vc_cipher *ctx, size_t count, const vc_shape *shapes,
                       const uint8_t *hashes, double *const *IR, uint16_t *const *D,
                       uint8_t *const *B, void *stream);
 
+/* ---- Statistics of Sec. III (integer reductions; formulas on the host) ----
+ * These need no context; each is synchronous (it synchronises `stream`
+ * before returning) and uses device memory it allocates and frees itself.
+ * Frames follow the conventions above (device, uint8 h x w x 3).
+ *
+ * vc_frame_histograms: 256-level intensity histogram of every channel of
+ * every frame (Sec. III-A, Eqs. 4-5: histogram variance and chi-square;
+ * Sec. III-C, Eq. 10: information entropy).  hist: device uint32
+ * [count][3][256], overwritten.  VC_EINVAL for bad shapes or NULL pointers. */
+int vc_frame_histograms(size_t count, const uint8_t *const *frames, const vc_shape *shapes, uint32_t *hist,
+                        void *stream);
+
+/* vc_block_histograms: histograms of `blocks` sub-blocks of block_h x
+ * block_w pixels per frame (Sec. III-C, Eq. 11: local Shannon entropy over
+ * k randomly chosen non-overlapping blocks of T_B pixels).  origins: HOST
+ * uint32 [count][blocks][2] = (row, column) of each block's top-left pixel;
+ * every block must lie inside its frame (else VC_EINVAL; overlap is the
+ * caller's choice).  hist: device uint32 [count][blocks][3][256]. */
+int vc_block_histograms(size_t count, const uint8_t *const *frames, const vc_shape *shapes, uint32_t blocks,
+                        uint32_t block_w, uint32_t block_h, const uint32_t *origins, uint32_t *hist, void *stream);
+
+/* vc_pair_moments: exact sums over adjacent pixel pairs (x at (r, c), y its
+ * neighbour) of x, y, x^2, y^2 and xy, per direction (0 horizontal (r, c+1),
+ * 1 vertical (r+1, c), 2 diagonal (r+1, c+1)) and channel -- the inputs of
+ * the correlation coefficient of Sec. III-B, Eqs. 6-9.  positions: HOST
+ * uint32 [count][npairs][2] = (r, c) with r < h-1 and c < w-1 (the same
+ * positions serve all three directions; else VC_EINVAL), or NULL for every
+ * such pixel.  moments: device uint64 [count][3 directions][3 channels][5],
+ * overwritten. */
+int vc_pair_moments(size_t count, const uint8_t *const *frames, const vc_shape *shapes, uint32_t npairs,
+                    const uint32_t *positions, uint64_t *moments, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

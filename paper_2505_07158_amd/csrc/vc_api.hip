@@ -1096,6 +1096,118 @@ int vc_autotune(vc_cipher *ctx, int decrypt, uint32_t w, uint32_t h, uint32_t fr
     return VC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Device copy of the frame table (and an optional host array of uint32
+// pairs), for the statistics entry points.  Synchronous upload; freed by
+// the destructor after the stream has been synchronised.
+struct StatUpload {
+    StatFrame *frames = nullptr;
+    uint32_t *pairs = nullptr;
+    ~StatUpload() {
+        if (pairs) (void)hipFree(pairs);
+        if (frames) (void)hipFree(frames);
+    }
+};
+
+int stat_frames(size_t count, const uint8_t *const *frames, const vc_shape *shapes, std::vector<StatFrame> &out) {
+    if (!frames || !shapes || count > 0xFFFFFFFFull) return VC_EINVAL;
+    out.resize(count);
+    for (size_t f = 0; f < count; ++f) {
+        const vc_shape &s = shapes[f];
+        if (!frames[f] || s.c != 3 || s.w < 1 || s.h < 1 || s.w > kMaxDim || s.h > kMaxDim) return VC_EINVAL;
+        out[f] = StatFrame{frames[f], s.w, s.h};
+    }
+    return VC_OK;
+}
+
+hipError_t upload(StatUpload &u, const std::vector<StatFrame> &fr, const uint32_t *pairs, size_t npairs_words) {
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&u.frames), sizeof(StatFrame) * fr.size());
+    if (e == hipSuccess) e = hipMemcpy(u.frames, fr.data(), sizeof(StatFrame) * fr.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess && pairs && npairs_words) {
+        e = hipMalloc(reinterpret_cast<void **>(&u.pairs), 4 * npairs_words);
+        if (e == hipSuccess) e = hipMemcpy(u.pairs, pairs, 4 * npairs_words, hipMemcpyHostToDevice);
+    }
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vc_frame_histograms(size_t count, const uint8_t *const *frames, const vc_shape *shapes, uint32_t *hist,
+                        void *stream) {
+    if (count == 0) return VC_OK;
+    if (!hist) return VC_EINVAL;
+    std::vector<StatFrame> fr;
+    int rc = stat_frames(count, frames, shapes, fr);
+    if (rc) return rc;
+    uint64_t max_bytes = 0;
+    for (auto &f : fr) max_bytes = std::max<uint64_t>(max_bytes, 3ull * f.w * f.h);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    StatUpload u;
+    hipError_t e = upload(u, fr, nullptr, 0);
+    if (e == hipSuccess) e = hipMemsetAsync(hist, 0, sizeof(uint32_t) * 3 * 256 * count, s);
+    if (e == hipSuccess) e = launch_frame_histograms(u.frames, static_cast<uint32_t>(count), max_bytes, hist, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return map_err(e);
+}
+
+int vc_block_histograms(size_t count, const uint8_t *const *frames, const vc_shape *shapes, uint32_t blocks,
+                        uint32_t block_w, uint32_t block_h, const uint32_t *origins, uint32_t *hist, void *stream) {
+    if (count == 0 || blocks == 0) return VC_OK;
+    if (!hist || !origins || block_w < 1 || block_h < 1) return VC_EINVAL;
+    std::vector<StatFrame> fr;
+    int rc = stat_frames(count, frames, shapes, fr);
+    if (rc) return rc;
+    for (size_t f = 0; f < count; ++f)
+        for (uint32_t m = 0; m < blocks; ++m) {
+            const uint32_t r = origins[2 * (f * blocks + m)], c = origins[2 * (f * blocks + m) + 1];
+            if (static_cast<uint64_t>(r) + block_h > fr[f].h || static_cast<uint64_t>(c) + block_w > fr[f].w)
+                return VC_EINVAL;
+        }
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    StatUpload u;
+    hipError_t e = upload(u, fr, origins, 2 * count * blocks);
+    if (e == hipSuccess)
+        e = launch_block_histograms(u.frames, static_cast<uint32_t>(count), blocks, block_w, block_h, u.pairs, hist, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return map_err(e);
+}
+
+int vc_pair_moments(size_t count, const uint8_t *const *frames, const vc_shape *shapes, uint32_t npairs,
+                    const uint32_t *positions, uint64_t *moments, void *stream) {
+    if (count == 0) return VC_OK;
+    if (!moments || (positions && npairs == 0)) return VC_EINVAL;
+    std::vector<StatFrame> fr;
+    int rc = stat_frames(count, frames, shapes, fr);
+    if (rc) return rc;
+    uint64_t max_pos = 0;
+    for (size_t f = 0; f < count; ++f) {
+        if (positions) {
+            for (uint32_t i = 0; i < npairs; ++i) {
+                const uint32_t r = positions[2 * (f * npairs + i)], c = positions[2 * (f * npairs + i) + 1];
+                if (static_cast<uint64_t>(r) + 1 >= fr[f].h || static_cast<uint64_t>(c) + 1 >= fr[f].w)
+                    return VC_EINVAL;
+            }
+            max_pos = npairs;
+        } else {
+            max_pos = std::max<uint64_t>(max_pos, static_cast<uint64_t>(fr[f].h - 1) * (fr[f].w - 1));
+        }
+    }
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    StatUpload u;
+    hipError_t e = upload(u, fr, positions, positions ? 2 * count * npairs : 0);
+    if (e == hipSuccess) e = hipMemsetAsync(moments, 0, sizeof(uint64_t) * 45 * count, s);
+    if (e == hipSuccess)
+        e = launch_pair_moments(u.frames, static_cast<uint32_t>(count), max_pos, npairs, u.pairs,
+                                reinterpret_cast<unsigned long long *>(moments), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return map_err(e);
+}
+
 int vc_set_confusion_passes(vc_cipher *ctx, uint32_t passes) {
     if (!ctx || (passes != 1 && passes != 2)) return VC_EINVAL;
     std::lock_guard<std::mutex> lk(ctx->mu);

@@ -73,6 +73,12 @@ struct ConfuseTuning {
 // Device flag bits (int at d_flags[0]).
 enum { FLAG_NONFINITE = 1 };
 
+// A frame for the statistics kernels (uint8, h x w x 3).
+struct StatFrame {
+    const uint8_t *data;
+    uint32_t w, h;
+};
+
 // Launchers (each in the translation unit of its kernel).
 hipError_t launch_sha256_subframes(const FrameDesc *d_desc, uint32_t count, uint32_t n,
                                    hipStream_t s);
@@ -97,5 +103,15 @@ hipError_t launch_shift(int decrypt, int pass, const FrameDesc *d_desc, uint32_t
 uint32_t shift_max_strip(uint32_t h, uint32_t lds_bytes);
 uint32_t shift_col_lds_bytes(uint32_t h, uint32_t strip);
 hipError_t shift_configure(uint32_t lds_limit);
+// Statistics (vc_stats.hip).  hist: count x 3 x 256 (frame) or count x
+// blocks x 3 x 256 (blocks), uint32; moments: count x 3 directions x 3
+// channels x 5 sums, uint64.  Frame histograms and moments are added to
+// their outputs (zero them first).
+hipError_t launch_frame_histograms(const StatFrame *d_frames, uint32_t count, uint64_t max_bytes, uint32_t *d_hist,
+                                   hipStream_t s);
+hipError_t launch_block_histograms(const StatFrame *d_frames, uint32_t count, uint32_t blocks, uint32_t bw,
+                                   uint32_t bh, const uint32_t *d_origins, uint32_t *d_hist, hipStream_t s);
+hipError_t launch_pair_moments(const StatFrame *d_frames, uint32_t count, uint64_t max_positions, uint32_t npos,
+                               const uint32_t *d_positions, unsigned long long *d_moments, hipStream_t s);
 
 }  // namespace vc

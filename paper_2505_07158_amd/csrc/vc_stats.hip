@@ -1,0 +1,167 @@
+// vc_stats.hip -- the integer reductions behind the statistical tests of
+// Sec. III of arXiv 2505.07158, on gfx950:
+//   * 256-level intensity histograms per channel of whole frames (Eqs. 4-5:
+//     histogram variance and chi-square; Eq. 10: information entropy),
+//   * the same over k sub-blocks of T_B pixels per frame (Eq. 11: local
+//     Shannon entropy),
+//   * exact integer moments (sums of x, y, x^2, y^2, xy) of adjacent pixel
+//     pairs in the horizontal, vertical and diagonal directions (Eqs. 6-9:
+//     correlation coefficients), over given pixel positions or over every
+//     pixel that has all three neighbours.
+// Positions and block origins are validated on the host before upload.
+// Everything here is integer arithmetic, so results are exact; the
+// floating-point formulas of the tests run on the host from these counts.
+#include "vc_internal.hpp"
+
+namespace vc {
+namespace {
+
+constexpr uint32_t kHistThreads = 256;
+constexpr uint32_t kHistChunk = 1u << 16;  // bytes of one frame per workgroup
+
+// Workgroup (frame f, chunk k): bytes [k*kHistChunk, ...) of frame f into an
+// LDS histogram (3 x 256 counters, channel = byte index mod 3), then added
+// to the frame's global histogram.
+__global__ __launch_bounds__(kHistThreads) void frame_histograms(const StatFrame *__restrict__ frames,
+                                                                uint32_t chunks_per_frame,
+                                                                uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[3 * 256];
+    const uint32_t f = blockIdx.x / chunks_per_frame, k = blockIdx.x - f * chunks_per_frame;
+    for (uint32_t i = threadIdx.x; i < 3 * 256; i += kHistThreads) h[i] = 0;
+    __syncthreads();
+    const StatFrame fr = frames[f];
+    const uint64_t L = 3ull * fr.w * fr.h;
+    const uint64_t b0 = static_cast<uint64_t>(k) * kHistChunk;
+    const uint64_t b1 = (b0 + kHistChunk < L) ? b0 + kHistChunk : L;
+    const VC_GLOBAL uint8_t *p = gmem(fr.data);
+    for (uint64_t b = b0 + threadIdx.x; b < b1; b += kHistThreads)
+        atomicAdd(&h[static_cast<uint32_t>(b % 3) * 256 + p[b]], 1u);
+    __syncthreads();
+    uint32_t *out = hist + 3ull * 256 * f;
+    for (uint32_t i = threadIdx.x; i < 3 * 256; i += kHistThreads)
+        if (h[i]) atomicAdd(&out[i], h[i]);
+}
+
+// Workgroup (frame f, block m): the bh x bw pixels at origin (r, c) of
+// frame f, channel by channel, into hist[f][m][c][256].
+__global__ __launch_bounds__(kHistThreads) void block_histograms(const StatFrame *__restrict__ frames,
+                                                                uint32_t blocks, uint32_t bw, uint32_t bh,
+                                                                const uint32_t *__restrict__ origins,
+                                                                uint32_t *__restrict__ hist) {
+    __shared__ uint32_t h[3 * 256];
+    const uint32_t f = blockIdx.x / blocks, m = blockIdx.x - f * blocks;
+    for (uint32_t i = threadIdx.x; i < 3 * 256; i += kHistThreads) h[i] = 0;
+    __syncthreads();
+    const StatFrame fr = frames[f];
+    const VC_GLOBAL uint32_t *o = gmem(origins) + 2ull * (static_cast<uint64_t>(f) * blocks + m);
+    const uint32_t r0 = o[0], c0 = o[1];
+    const VC_GLOBAL uint8_t *p = gmem(fr.data);
+    const uint32_t n = bw * bh * 3;
+    for (uint32_t t = threadIdx.x; t < n; t += kHistThreads) {
+        const uint32_t row = t / (3 * bw), rem = t - row * 3 * bw;
+        const uint64_t off = (static_cast<uint64_t>(r0 + row) * fr.w + c0) * 3 + rem;
+        atomicAdd(&h[(rem % 3) * 256 + p[off]], 1u);
+    }
+    __syncthreads();
+    VC_GLOBAL uint32_t *out = gmem(hist) + 3ull * 256 * (static_cast<uint64_t>(f) * blocks + m);
+    for (uint32_t i = threadIdx.x; i < 3 * 256; i += kHistThreads) out[i] = h[i];
+}
+
+// Moments of adjacent pairs: for direction d (0 horizontal: (r, c+1),
+// 1 vertical: (r+1, c), 2 diagonal: (r+1, c+1)) and channel ch, the sums
+// of x, y, x^2, y^2, xy over the pixel positions of frame f.  Each lane
+// accumulates in 64-bit registers; lanes of a workgroup meet in LDS; one
+// atomic add per sum per workgroup.
+constexpr uint32_t kMomThreads = 256;
+constexpr uint32_t kMomPerGroup = 4096;  // positions per workgroup
+
+__global__ __launch_bounds__(kMomThreads) void pair_moments(const StatFrame *__restrict__ frames,
+                                                            uint32_t groups_per_frame, uint32_t npos,
+                                                            const uint32_t *__restrict__ positions,
+                                                            unsigned long long *__restrict__ moments) {
+    __shared__ unsigned long long acc[45];
+    const uint32_t f = blockIdx.x / groups_per_frame, g = blockIdx.x - f * groups_per_frame;
+    for (uint32_t i = threadIdx.x; i < 45; i += kMomThreads) acc[i] = 0;
+    __syncthreads();
+    const StatFrame fr = frames[f];
+    const VC_GLOBAL uint8_t *p = gmem(fr.data);
+    const uint32_t w = fr.w, h = fr.h;
+    // without positions: every pixel (r, c) with r < h-1 and c < w-1 takes
+    // part in all three directions
+    const uint64_t total = positions ? npos : static_cast<uint64_t>(h - 1) * (w - 1);
+    unsigned long long s[45];
+#pragma unroll
+    for (int i = 0; i < 45; ++i) s[i] = 0;
+    const uint64_t i0 = static_cast<uint64_t>(g) * kMomPerGroup;
+    const uint64_t i1 = (i0 + kMomPerGroup < total) ? i0 + kMomPerGroup : total;
+    for (uint64_t i = i0 + threadIdx.x; i < i1; i += kMomThreads) {
+        uint32_t r, c;
+        if (positions) {
+            const VC_GLOBAL uint32_t *q = gmem(positions) + 2ull * (static_cast<uint64_t>(f) * npos + i);
+            r = q[0];
+            c = q[1];
+        } else {
+            const uint32_t i32 = static_cast<uint32_t>(i);  // (h-1)(w-1) < 2^32
+            r = i32 / (w - 1);
+            c = i32 - r * (w - 1);
+        }
+        const uint64_t base = (static_cast<uint64_t>(r) * w + c) * 3;
+        const uint64_t nb[3] = {base + 3, base + 3ull * w, base + 3ull * w + 3};
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const unsigned long long x = p[base + ch];
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                const unsigned long long y = p[nb[d] + ch];
+                unsigned long long *t = s + 15 * d + 5 * ch;
+                t[0] += x;
+                t[1] += y;
+                t[2] += x * x;
+                t[3] += y * y;
+                t[4] += x * y;
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 45; ++i) {
+        unsigned long long v = s[i];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if ((threadIdx.x & 63) == 0) atomicAdd(&acc[i], v);
+    }
+    __syncthreads();
+    unsigned long long *out = moments + 45ull * f;
+    for (uint32_t i = threadIdx.x; i < 45; i += kMomThreads) atomicAdd(&out[i], acc[i]);
+}
+
+}  // namespace
+
+hipError_t launch_frame_histograms(const StatFrame *d_frames, uint32_t count, uint64_t max_bytes, uint32_t *d_hist,
+                                   hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    const uint64_t chunks = (max_bytes + kHistChunk - 1) / kHistChunk;
+    if (chunks * count > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(frame_histograms, dim3(static_cast<uint32_t>(chunks * count)), dim3(kHistThreads), 0, s,
+                       d_frames, static_cast<uint32_t>(chunks), d_hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_block_histograms(const StatFrame *d_frames, uint32_t count, uint32_t blocks, uint32_t bw,
+                                   uint32_t bh, const uint32_t *d_origins, uint32_t *d_hist, hipStream_t s) {
+    if (count == 0 || blocks == 0) return hipSuccess;
+    if (static_cast<uint64_t>(blocks) * count > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(block_histograms, dim3(count * blocks), dim3(kHistThreads), 0, s, d_frames, blocks, bw, bh,
+                       d_origins, d_hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_moments(const StatFrame *d_frames, uint32_t count, uint64_t max_positions, uint32_t npos,
+                               const uint32_t *d_positions, unsigned long long *d_moments, hipStream_t s) {
+    if (count == 0 || max_positions == 0) return hipSuccess;
+    const uint64_t groups = (max_positions + kMomPerGroup - 1) / kMomPerGroup;
+    if (groups * count > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(pair_moments, dim3(static_cast<uint32_t>(groups * count)), dim3(kMomThreads), 0, s, d_frames,
+                       static_cast<uint32_t>(groups), npos, d_positions, d_moments);
+    return hipGetLastError();
+}
+
+}  // namespace vc

@@ -58,10 +58,12 @@ class Scheduler:
     batch has completed).  At most ``max_inflight`` batches of a kind (of a
     kind and class, with ``batch_class``) are in flight."""
 
-    def __init__(self, launch: Callable[[str, List[Request]], object], hbm_budget: int, max_inflight: int = 2,
+    def __init__(self, launch: Callable[[str, List[Request]], object], hbm_budget: int, max_inflight=2,
                  max_batch: int = 512, clock: Callable[[], float] = time.perf_counter,
                  batch_class: Optional[Callable[[Request], object]] = None, max_stream_inflight: int = 0):
         self.launch = launch
+        # max_inflight: an int, or a function (kind, class) -> int
+        self.max_inflight = max_inflight if callable(max_inflight) else (lambda kind, cls, m=max_inflight: m)
         # at most this many frames of one stream in flight (0 = no limit), e.g.
         # to bound a per-stream ring of output buffers
         self.max_stream_inflight = max_stream_inflight
@@ -70,7 +72,6 @@ class Scheduler:
         # batch, so a batch's completion is not held back by slower frames.
         self.batch_class = batch_class
         self.hbm_budget = hbm_budget
-        self.max_inflight = max_inflight
         self.max_batch = max_batch
         self.clock = clock
         self.pending: Dict[str, Deque[Request]] = {"enc": collections.deque(), "dec": collections.deque()}
@@ -130,7 +131,7 @@ class Scheduler:
                 rc = self._class_of(r)
                 taken = want - self.next_seq[key]   # frames of this stream already in this batch
                 if full or r.seq != want or (batch and rc != cls) or \
-                        (not batch and self._inflight_of(kind, rc) >= self.max_inflight) or \
+                        (not batch and self._inflight_of(kind, rc) >= self.max_inflight(kind, rc)) or \
                         (self.max_stream_inflight and
                          self.stream_inflight[key] + taken >= self.max_stream_inflight):
                     left.append(r)
@@ -188,7 +189,7 @@ class GpuBackend:
     device streams."""
 
     def __init__(self, key32: bytes, gamma: float, n: int, max_streams: int, scratch_bytes: int,
-                 overlap: Optional[Tuple[int, int, int]] = None, device_streams: int = 2,
+                 overlap: Optional[Tuple[int, int, int]] = None, device_streams=2,
                  classes: Optional[Sequence[object]] = None,
                  batch_class: Optional[Callable[[Request], object]] = None):
         import torch
@@ -208,7 +209,8 @@ class GpuBackend:
                 if overlap:
                     c.overlap(*overlap)
                 self.ctx[(kind, cls)] = c
-                self.streams[(kind, cls)] = [torch.cuda.Stream() for _ in range(device_streams)]
+                ns = device_streams(kind, cls) if callable(device_streams) else device_streams
+                self.streams[(kind, cls)] = [torch.cuda.Stream() for _ in range(ns)]
                 self.turn[(kind, cls)] = 0
 
     def footprint(self, w: int, h: int) -> int:

@@ -69,6 +69,10 @@ def _load() -> C.CDLL:
     L.vc_set_tuning.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_int]
     L.vc_set_overlap.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_uint32]
     L.vc_set_confusion_passes.argtypes = [vp, C.c_uint32]
+    L.vc_frame_histograms.argtypes = [C.c_size_t, C.POINTER(vp), C.POINTER(VcShape), vp, vp]
+    L.vc_block_histograms.argtypes = [C.c_size_t, C.POINTER(vp), C.POINTER(VcShape), C.c_uint32, C.c_uint32,
+                                      C.c_uint32, vp, vp, vp]
+    L.vc_pair_moments.argtypes = [C.c_size_t, C.POINTER(vp), C.POINTER(VcShape), C.c_uint32, vp, vp, vp]
     L.vc_autotune.argtypes = [vp, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32),
                               C.POINTER(C.c_uint32)]
     L.vc_scratch_per_frame.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
@@ -82,6 +86,7 @@ def _load() -> C.CDLL:
                  "cipher_stream_get_state", "cipher_stream_set_state", "cipher_status",
                  "vc_profile_enable", "vc_profile_read", "vc_profile_reset", "vc_set_tuning",
                  "vc_set_overlap", "vc_set_confusion_passes", "vc_autotune",
+                 "vc_frame_histograms", "vc_block_histograms", "vc_pair_moments",
                  "vc_debug_confuse", "vc_debug_keysched", "vc_key_from_bytes"):
         getattr(L, name).restype = C.c_int
     return L
@@ -292,6 +297,55 @@ def vc_autotune(ctx: int, decrypt: bool, w: int, h: int, frames: int) -> Tuple[i
     _check(lib.vc_autotune(C.c_void_p(ctx), 1 if decrypt else 0, w, h, frames, C.byref(strip), C.byref(threads)),
            "vc_autotune")
     return strip.value, threads.value
+
+
+def vc_frame_histograms(frames: Sequence[torch.Tensor], stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """Per-channel 256-level histograms: int64 tensor (count, 3, 256) on the device."""
+    for t in frames:
+        _check_frame(t)
+    hist = torch.empty((len(frames), 3, 256), dtype=torch.int32, device=frames[0].device)
+    _check(lib.vc_frame_histograms(len(frames), _ptrs(frames), _shapes(frames, [0] * len(frames), [0] * len(frames)),
+                                   C.c_void_p(hist.data_ptr()), C.c_void_p(_stream_handle(stream))),
+           "vc_frame_histograms")
+    return hist.to(torch.int64)
+
+
+def vc_block_histograms(frames: Sequence[torch.Tensor], origins, block_w: int, block_h: int,
+                        stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """Histograms of sub-blocks; origins: uint32 array (count, blocks, 2) of (row, col) on the host.
+    Returns int64 (count, blocks, 3, 256) on the device."""
+    import numpy as np
+    for t in frames:
+        _check_frame(t)
+    o = np.ascontiguousarray(origins, dtype=np.uint32)
+    if o.ndim != 3 or o.shape[0] != len(frames) or o.shape[2] != 2:
+        raise ValueError("origins must have shape (count, blocks, 2)")
+    blocks = o.shape[1]
+    hist = torch.empty((len(frames), blocks, 3, 256), dtype=torch.int32, device=frames[0].device)
+    _check(lib.vc_block_histograms(len(frames), _ptrs(frames), _shapes(frames, [0] * len(frames), [0] * len(frames)),
+                                   blocks, block_w, block_h, C.c_void_p(o.ctypes.data), C.c_void_p(hist.data_ptr()),
+                                   C.c_void_p(_stream_handle(stream))), "vc_block_histograms")
+    return hist.to(torch.int64)
+
+
+def vc_pair_moments(frames: Sequence[torch.Tensor], positions=None,
+                    stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """Sums of x, y, x^2, y^2, xy over adjacent pairs: int64 (count, 3 directions, 3 channels, 5).
+    positions: uint32 array (count, npairs, 2) of (row, col) on the host, or None for every pixel."""
+    import numpy as np
+    for t in frames:
+        _check_frame(t)
+    npairs, ptr, keep = 0, None, None
+    if positions is not None:
+        keep = np.ascontiguousarray(positions, dtype=np.uint32)
+        if keep.ndim != 3 or keep.shape[0] != len(frames) or keep.shape[2] != 2:
+            raise ValueError("positions must have shape (count, npairs, 2)")
+        npairs, ptr = keep.shape[1], keep.ctypes.data
+    mom = torch.empty((len(frames), 3, 3, 5), dtype=torch.int64, device=frames[0].device)
+    _check(lib.vc_pair_moments(len(frames), _ptrs(frames), _shapes(frames, [0] * len(frames), [0] * len(frames)),
+                               npairs, C.c_void_p(ptr), C.c_void_p(mom.data_ptr()), C.c_void_p(_stream_handle(stream))),
+           "vc_pair_moments")
+    return mom
 
 
 def vc_scratch_per_frame(w: int, h: int, n: int) -> int:
