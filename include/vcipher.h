@@ -274,6 +274,16 @@ int vc_block_histograms(size_t count, const uint8_t *const *frames, const vc_sha
 int vc_pair_moments(size_t count, const uint8_t *const *frames, const vc_shape *shapes, uint32_t npairs,
                     const uint32_t *positions, uint64_t *moments, void *stream);
 
+/* vc_frame_diff: per channel of each pair of frames a[i], b[i] (both of
+ * shapes[i]): the number of differing bytes, the sum of |a - b|, the sum of
+ * (a - b)^2 and the number of differing bits -- the counts behind NPCR and
+ * UACI (Sec. IV-B, Eqs. 14-16) and behind the PSNR of a frame decrypted
+ * after a cropping attack or channel noise (Sec. IV-C).  out: device uint64
+ * [count][3 channels][4], overwritten.  VC_EINVAL for bad shapes or NULL
+ * pointers. */
+int vc_frame_diff(size_t count, const uint8_t *const *a, const uint8_t *const *b, const vc_shape *shapes,
+                  uint64_t *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,4 +1,5 @@
-"""Statistical tests of Sec. III of arXiv 2505.07158, written out plainly
+"""Statistical tests of Sec. III and the difference measures of Sec. IV of
+arXiv 2505.07158, written out plainly
 (numpy, fp64) from their definitions.  TEST INFRASTRUCTURE ONLY: the
 library computes the same quantities from integer reductions on the GPU;
 this module is what its tests compare against.
@@ -90,3 +91,41 @@ def correlation(frame: np.ndarray, channel: int, direction: int, positions=None)
     dx = np.sum((x - ex) ** 2) / n
     dy = np.sum((y - ey) ** 2) / n
     return float(cov / np.sqrt(dx * dy))
+
+
+# ---------------------------------------------------------------------------
+# differences between two frames (Sec. IV)
+# ---------------------------------------------------------------------------
+
+def frame_diff(a: np.ndarray, b: np.ndarray) -> np.ndarray:
+    """(3, 4) per channel: differing bytes, sum |a-b|, sum (a-b)^2, differing bits."""
+    out = np.zeros((3, 4), dtype=np.int64)
+    for c in range(3):
+        x = a[..., c].astype(np.int64).ravel()
+        y = b[..., c].astype(np.int64).ravel()
+        d = x - y
+        out[c, 0] = np.count_nonzero(d)
+        out[c, 1] = np.abs(d).sum()
+        out[c, 2] = (d * d).sum()
+        out[c, 3] = np.unpackbits((x ^ y).astype(np.uint8)).sum()
+    return out
+
+
+def npcr(a: np.ndarray, b: np.ndarray, c: int) -> float:
+    """Eqs. 14 and 16: percentage of positions whose values differ, one channel."""
+    return 100.0 * float(np.mean(a[..., c] != b[..., c]))
+
+
+def uaci(a: np.ndarray, b: np.ndarray, c: int) -> float:
+    """Eq. 15: mean absolute difference over the largest value 255, in percent."""
+    d = np.abs(a[..., c].astype(np.float64) - b[..., c].astype(np.float64))
+    return 100.0 * float(np.mean(d / 255.0))
+
+
+def psnr(a: np.ndarray, b: np.ndarray, c=None) -> float:
+    """Peak signal-to-noise ratio 10 log10(255^2 / MSE) in dB, over one channel
+    or (c = None) over all three; infinite for identical data."""
+    x = a.astype(np.float64) if c is None else a[..., c].astype(np.float64)
+    y = b.astype(np.float64) if c is None else b[..., c].astype(np.float64)
+    mse = float(np.mean((x - y) ** 2))
+    return float("inf") if mse == 0 else 10.0 * np.log10(255.0 ** 2 / mse)

@@ -1208,6 +1208,29 @@ int vc_pair_moments(size_t count, const uint8_t *const *frames, const vc_shape *
     return map_err(e);
 }
 
+int vc_frame_diff(size_t count, const uint8_t *const *a, const uint8_t *const *b, const vc_shape *shapes,
+                  uint64_t *out, void *stream) {
+    if (count == 0) return VC_OK;
+    if (!out || !b) return VC_EINVAL;
+    std::vector<StatFrame> fa, fb;
+    int rc = stat_frames(count, a, shapes, fa);
+    if (rc) return rc;
+    rc = stat_frames(count, b, shapes, fb);
+    if (rc) return rc;
+    uint64_t max_bytes = 0;
+    for (auto &f : fa) max_bytes = std::max<uint64_t>(max_bytes, 3ull * f.w * f.h);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    StatUpload ua, ub;
+    hipError_t e = upload(ua, fa, nullptr, 0);
+    if (e == hipSuccess) e = upload(ub, fb, nullptr, 0);
+    if (e == hipSuccess) e = hipMemsetAsync(out, 0, sizeof(uint64_t) * 12 * count, s);
+    if (e == hipSuccess)
+        e = launch_frame_diff(ua.frames, ub.frames, static_cast<uint32_t>(count), max_bytes,
+                              reinterpret_cast<unsigned long long *>(out), s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    return map_err(e);
+}
+
 int vc_set_confusion_passes(vc_cipher *ctx, uint32_t passes) {
     if (!ctx || (passes != 1 && passes != 2)) return VC_EINVAL;
     std::lock_guard<std::mutex> lk(ctx->mu);

@@ -113,5 +113,7 @@ hipError_t launch_block_histograms(const StatFrame *d_frames, uint32_t count, ui
                                    uint32_t bh, const uint32_t *d_origins, uint32_t *d_hist, hipStream_t s);
 hipError_t launch_pair_moments(const StatFrame *d_frames, uint32_t count, uint64_t max_positions, uint32_t npos,
                                const uint32_t *d_positions, unsigned long long *d_moments, hipStream_t s);
+hipError_t launch_frame_diff(const StatFrame *d_a, const StatFrame *d_b, uint32_t count, uint64_t max_bytes,
+                             unsigned long long *d_out, hipStream_t s);
 
 }  // namespace vc

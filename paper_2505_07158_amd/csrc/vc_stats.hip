@@ -7,7 +7,9 @@
 //   * exact integer moments (sums of x, y, x^2, y^2, xy) of adjacent pixel
 //     pairs in the horizontal, vertical and diagonal directions (Eqs. 6-9:
 //     correlation coefficients), over given pixel positions or over every
-//     pixel that has all three neighbours.
+//     pixel that has all three neighbours,
+//   * difference counts of two frames (Sec. IV: NPCR and UACI of Eqs. 14-16,
+//     and the PSNR of frames decrypted after cropping or channel noise).
 // Positions and block origins are validated on the host before upload.
 // Everything here is integer arithmetic, so results are exact; the
 // floating-point formulas of the tests run on the host from these counts.
@@ -34,8 +36,13 @@ __global__ __launch_bounds__(kHistThreads) void frame_histograms(const StatFrame
     const uint64_t b0 = static_cast<uint64_t>(k) * kHistChunk;
     const uint64_t b1 = (b0 + kHistChunk < L) ? b0 + kHistChunk : L;
     const VC_GLOBAL uint8_t *p = gmem(fr.data);
-    for (uint64_t b = b0 + threadIdx.x; b < b1; b += kHistThreads)
-        atomicAdd(&h[static_cast<uint32_t>(b % 3) * 256 + p[b]], 1u);
+    // the channel of byte b is b mod 3; the stride is 1 mod 3
+    static_assert(kHistThreads % 3 == 1, "the channel update assumes a stride of 1 mod 3");
+    uint32_t c = static_cast<uint32_t>((b0 + threadIdx.x) % 3);
+    for (uint64_t b = b0 + threadIdx.x; b < b1; b += kHistThreads) {
+        atomicAdd(&h[c * 256 + p[b]], 1u);
+        c = (c == 2) ? 0 : c + 1;
+    }
     __syncthreads();
     uint32_t *out = hist + 3ull * 256 * f;
     for (uint32_t i = threadIdx.x; i < 3 * 256; i += kHistThreads)
@@ -133,7 +140,66 @@ __global__ __launch_bounds__(kMomThreads) void pair_moments(const StatFrame *__r
     for (uint32_t i = threadIdx.x; i < 45; i += kMomThreads) atomicAdd(&out[i], acc[i]);
 }
 
+// Workgroup (frame f, chunk k): per channel, over bytes [k*kHistChunk, ...)
+// of the frames a[f] and b[f] (same shape): the number of differing bytes,
+// the sum of |a - b|, the sum of (a - b)^2 and the number of differing bits
+// -- the counts behind NPCR and UACI (Sec. IV-B, Eqs. 14-16) and the PSNR of
+// a decryption after cropping or noise (Sec. IV-C).  A lane sees at most
+// kHistChunk / kHistThreads bytes, so its 32-bit sums cannot overflow
+// (256 * 255^2 < 2^24), nor can a wave's (64 times that).
+__global__ __launch_bounds__(kHistThreads) void frame_diff(const StatFrame *__restrict__ fa,
+                                                          const StatFrame *__restrict__ fb,
+                                                          uint32_t chunks_per_frame,
+                                                          unsigned long long *__restrict__ out) {
+    __shared__ unsigned long long acc[12];
+    const uint32_t f = blockIdx.x / chunks_per_frame, k = blockIdx.x - f * chunks_per_frame;
+    if (threadIdx.x < 12) acc[threadIdx.x] = 0;
+    __syncthreads();
+    const StatFrame A = fa[f];
+    const uint64_t L = 3ull * A.w * A.h;
+    const uint64_t b0 = static_cast<uint64_t>(k) * kHistChunk;
+    const uint64_t b1 = (b0 + kHistChunk < L) ? b0 + kHistChunk : L;
+    const VC_GLOBAL uint8_t *pa = gmem(A.data);
+    const VC_GLOBAL uint8_t *pb = gmem(fb[f].data);
+    uint32_t s[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) s[i] = 0;
+    static_assert(kHistThreads % 3 == 1, "the channel update below assumes a stride of 1 mod 3");
+    uint32_t c = static_cast<uint32_t>((b0 + threadIdx.x) % 3);
+    for (uint64_t b = b0 + threadIdx.x; b < b1; b += kHistThreads, c = (c == 2) ? 0 : c + 1) {
+        const uint32_t x = pa[b], y = pb[b];
+        const uint32_t d = x > y ? x - y : y - x;
+        // select by channel without dynamic register indexing
+#pragma unroll
+        for (uint32_t ch = 0; ch < 3; ++ch) {
+            const bool on = (ch == c);
+            s[4 * ch + 0] += on ? (d != 0) : 0u;
+            s[4 * ch + 1] += on ? d : 0u;
+            s[4 * ch + 2] += on ? d * d : 0u;
+            s[4 * ch + 3] += on ? static_cast<uint32_t>(__popc(x ^ y)) : 0u;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        uint32_t v = s[i];
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+        if ((threadIdx.x & 63) == 0 && v) atomicAdd(&acc[i], static_cast<unsigned long long>(v));
+    }
+    __syncthreads();
+    if (threadIdx.x < 12 && acc[threadIdx.x]) atomicAdd(&out[12ull * f + threadIdx.x], acc[threadIdx.x]);
+}
+
 }  // namespace
+
+hipError_t launch_frame_diff(const StatFrame *d_a, const StatFrame *d_b, uint32_t count, uint64_t max_bytes,
+                             unsigned long long *d_out, hipStream_t s) {
+    if (count == 0) return hipSuccess;
+    const uint64_t chunks = (max_bytes + kHistChunk - 1) / kHistChunk;
+    if (chunks * count > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(frame_diff, dim3(static_cast<uint32_t>(chunks * count)), dim3(kHistThreads), 0, s, d_a, d_b,
+                       static_cast<uint32_t>(chunks), d_out);
+    return hipGetLastError();
+}
 
 hipError_t launch_frame_histograms(const StatFrame *d_frames, uint32_t count, uint64_t max_bytes, uint32_t *d_hist,
                                    hipStream_t s) {

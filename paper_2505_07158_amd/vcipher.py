@@ -73,6 +73,7 @@ def _load() -> C.CDLL:
     L.vc_block_histograms.argtypes = [C.c_size_t, C.POINTER(vp), C.POINTER(VcShape), C.c_uint32, C.c_uint32,
                                       C.c_uint32, vp, vp, vp]
     L.vc_pair_moments.argtypes = [C.c_size_t, C.POINTER(vp), C.POINTER(VcShape), C.c_uint32, vp, vp, vp]
+    L.vc_frame_diff.argtypes = [C.c_size_t, C.POINTER(vp), C.POINTER(vp), C.POINTER(VcShape), vp, vp]
     L.vc_autotune.argtypes = [vp, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32),
                               C.POINTER(C.c_uint32)]
     L.vc_scratch_per_frame.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
@@ -86,7 +87,7 @@ def _load() -> C.CDLL:
                  "cipher_stream_get_state", "cipher_stream_set_state", "cipher_status",
                  "vc_profile_enable", "vc_profile_read", "vc_profile_reset", "vc_set_tuning",
                  "vc_set_overlap", "vc_set_confusion_passes", "vc_autotune",
-                 "vc_frame_histograms", "vc_block_histograms", "vc_pair_moments",
+                 "vc_frame_histograms", "vc_block_histograms", "vc_pair_moments", "vc_frame_diff",
                  "vc_debug_confuse", "vc_debug_keysched", "vc_key_from_bytes"):
         getattr(L, name).restype = C.c_int
     return L
@@ -346,6 +347,25 @@ def vc_pair_moments(frames: Sequence[torch.Tensor], positions=None,
                                npairs, C.c_void_p(ptr), C.c_void_p(mom.data_ptr()), C.c_void_p(_stream_handle(stream))),
            "vc_pair_moments")
     return mom
+
+
+def vc_frame_diff(a: Sequence[torch.Tensor], b: Sequence[torch.Tensor],
+                  stream: Optional[torch.cuda.Stream] = None) -> torch.Tensor:
+    """Per channel of each frame pair: [differing bytes, sum |a-b|, sum (a-b)^2, differing bits],
+    int64 (count, 3, 4) on the device."""
+    if len(a) != len(b):
+        raise ValueError("a and b must hold the same number of frames")
+    for x, y in zip(a, b):
+        _check_frame(x)
+        _check_frame(y)
+        if x.shape != y.shape:
+            raise ValueError("frame pairs must have the same shape")
+    if not a:
+        return torch.empty((0, 3, 4), dtype=torch.int64)
+    out = torch.empty((len(a), 3, 4), dtype=torch.int64, device=a[0].device)
+    _check(lib.vc_frame_diff(len(a), _ptrs(a), _ptrs(b), _shapes(a, [0] * len(a), [0] * len(a)),
+                             C.c_void_p(out.data_ptr()), C.c_void_p(_stream_handle(stream))), "vc_frame_diff")
+    return out
 
 
 def vc_scratch_per_frame(w: int, h: int, n: int) -> int:
