@@ -24,6 +24,7 @@ oracle timed on this host's cores on a bounded sample.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -48,8 +49,11 @@ def parse():
     ap.add_argument("--max-batch", type=int, default=256, help="serving: frames per batch at most")
     ap.add_argument("--plain-frames", type=int, default=400, help="serving: arrivals replayed one frame per launch")
     ap.add_argument("--inflight", type=int, default=2, help="serving: batches in flight per kind and resolution")
-    ap.add_argument("--inflight-4k", type=int, default=0,
+    ap.add_argument("--inflight-4k", type=int, default=1,
                     help="serving: batches in flight per kind at 3840x2160 (0 = --inflight)")
+    ap.add_argument("--hash-first", type=int, default=0,
+                    help="serving: 1 = hash each encrypt request on arrival, then chain/keystream/confusion in "
+                    "stream order (encrypt_frames_hashed); 0 = one encrypt_frames call per batch")
     ap.add_argument("--serve-parts", type=int, default=1, help="serving: parts per call (vc_set_overlap)")
     ap.add_argument("--serve-side", type=int, default=0, help="serving: side streams per context (vc_set_overlap)")
     ap.add_argument("--steps", type=int, default=10)
@@ -176,7 +180,7 @@ def run_serving(args) -> None:
 
     R = 8   # output buffers per stream (frames of a stream in flight at most)
 
-    def make_backend(max_inflight):
+    def make_backend(max_inflight, hash_first):
         cls = (lambda r: (streams[r.stream]["w"], streams[r.stream]["h"]))
         # one context pair per resolution, each with its chain stream and
         # --serve-side side streams, and one device stream per in-flight batch
@@ -184,24 +188,28 @@ def run_serving(args) -> None:
         return cls, GpuBackend(kb, gamma, n, max_streams=S, scratch_bytes=max(budget // len(res_set), 1 << 30),
                                overlap=(args.serve_parts, args.serve_side, 2),
                                device_streams=lambda kind, c: max(max_inflight(kind, c), 1),
-                               classes=res_set, batch_class=cls)
+                               classes=res_set, batch_class=cls, hash_first=hash_first)
 
-    # warm-up: every kernel variant the trace uses is loaded and run once
-    _, wb = make_backend(lambda kind, c: 1)
-    for s, st in enumerate(streams):
-        if all(streams[x]["w"] != st["w"] or streams[x]["h"] != st["h"] for x in range(s)):
-            for kind in ("enc", "dec"):
-                f = pool[s][0]
-                h32 = torch.zeros(32, dtype=torch.uint8, device=dev)
-                wb.launch(kind, [Request(stream=s, seq=0, kind=kind, frame=f, out=torch.empty_like(f), hashes=h32)])
-    torch.cuda.synchronize()
-    wb.close()
     outs = [torch.empty((R,) + tuple(pool[s].shape[1:]), dtype=torch.uint8, device=dev) for s in range(S)]
     first = [torch.empty_like(pool[s]) for s in range(S)]   # decrypt outputs of seq < P, kept for the check
     hring = [torch.empty((R, 32), dtype=torch.uint8, device=dev) for _ in range(S)]
 
-    def one_run(trace, max_batch, max_inflight):
-        cls, be = make_backend(max_inflight)
+    def one_run(trace, max_batch, max_inflight, hash_first):
+        cls, be = make_backend(max_inflight, hash_first)
+        # warm-up on the backend itself (every kernel variant, every device
+        # stream of each kind and resolution), then the chains back to the key
+        for s, st in enumerate(streams):
+            if all(streams[x]["w"] != st["w"] or streams[x]["h"] != st["h"] for x in range(s)):
+                for kind in (("hash", "enc", "dec") if hash_first else ("enc", "dec")):
+                    for q in range(max_inflight(kind, (st["w"], st["h"]))):
+                        f = pool[s][0]
+                        h32 = torch.zeros(32, dtype=torch.uint8, device=dev)
+                        r = Request(stream=s, seq=q, kind="enc" if kind == "hash" else kind, frame=f,
+                                    out=torch.empty_like(f), hashes=h32, hashed=hash_first)
+                        be.launch(kind, [r])
+        torch.cuda.synchronize()
+        be.reset_chains(range(S))
+        be.launch_seconds = 0.0
         dec_src = {}
         sender = V.Cipher.from_bytes(kb, gamma, n, max_streams=S, scratch_bytes=max(budget // 4, 1 << 30))
         for s, st in enumerate(streams):
@@ -211,9 +219,13 @@ def run_serving(args) -> None:
         torch.cuda.synchronize()
         sender.close()
         sched = Scheduler(be.launch, hbm_budget=budget, max_inflight=max_inflight, max_batch=max_batch,
-                          batch_class=cls, max_stream_inflight=R)
+                          batch_class=cls, max_stream_inflight=R, hash_first=hash_first)
         reqs = []
         i = 0
+        # no cyclic garbage collection while the trace runs (a full
+        # collection over the growing request list would pause the loop)
+        gc.collect()
+        gc.disable()
         t0 = time.perf_counter()
         while i < len(trace) or not sched.idle():
             now = time.perf_counter() - t0
@@ -234,6 +246,7 @@ def run_serving(args) -> None:
                 time.sleep(0.0001)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        gc.enable()
         # decrypt requests whose ciphertext matches their sequence number
         ok = all(torch.equal(first[r.stream][r.seq], pool[r.stream][r.seq]) for r in reqs
                  if r.kind == "dec" and r.seq < P)
@@ -261,10 +274,10 @@ def run_serving(args) -> None:
     # (at 2: 16 device streams + 8 chain streams, within 32 hardware queues)
     infl4k = args.inflight_4k or args.inflight
     infl = lambda kind, c: max(1, infl4k if c == (3840, 2160) else args.inflight)
-    batched = one_run(trace, args.max_batch, infl)
+    batched = one_run(trace, args.max_batch, infl, bool(args.hash_first))
     # The plain per-frame path cannot keep up with the offered load; it runs
     # the first --plain-frames arrivals of the same trace.
-    plain = one_run(trace[:args.plain_frames], 1, lambda kind, c: 1)
+    plain = one_run(trace[:args.plain_frames], 1, lambda kind, c: 1, False)
     offered = len(trace) / args.duration
     line = {"metric": "serving: p50/p99 arrival-to-completion latency (ms), frames/s", "value": batched["p99_ms"],
             "unit": "ms (p99)", "n_gpus": 1, "higher_is_better": False, "dtype": "u8", "data": "synthetic",
@@ -273,7 +286,7 @@ def run_serving(args) -> None:
                                    f"{args.duration} s trace", "n": n, "offered_frames_per_s": round(offered, 1),
                        "hbm_budget_gb": args.hbm_budget_gb, "max_batch": args.max_batch,
                        "inflight_batches_per_kind_and_resolution": f"{args.inflight} ({infl4k} at 3840x2160)",
-                       "batch_class": "resolution",
+                       "batch_class": "resolution", "hash_first": bool(args.hash_first),
                        "parts": args.serve_parts, "side_streams": args.serve_side},
             "continuous_batching": batched, "plain_per_frame": plain}
     print(json.dumps(line), flush=True)

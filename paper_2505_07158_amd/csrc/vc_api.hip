@@ -45,7 +45,7 @@ constexpr uint32_t kMaxN = 1024;
 constexpr double kGammaLo = -1.52;
 constexpr double kGammaHi = -0.06;
 constexpr uint32_t kMaxDim = 65535;
-constexpr int kRing = 4;
+constexpr int kRing = 8;
 constexpr int kMaxSide = 8;
 constexpr int kMaxSlots = 4;
 

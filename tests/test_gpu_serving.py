@@ -13,8 +13,8 @@ from workload.synth import SynthVideo, key_bytes
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("per_class", [False, True])
-def test_results_alone_equal_results_in_the_mix(per_class):
+@pytest.mark.parametrize("per_class,hash_first", [(False, False), (True, False), (True, True)])
+def test_results_alone_equal_results_in_the_mix(per_class, hash_first):
     dev = require_gpu()
     from paper_2505_07158_amd import vcipher as V
     from paper_2505_07158_amd.serving import GpuBackend, Request, Scheduler
@@ -45,8 +45,9 @@ def test_results_alone_equal_results_in_the_mix(per_class):
     shape_of.update({("dec", s): sh for s, sh in enumerate(dec_shapes)})
     cls = (lambda r: shape_of[(r.kind, r.stream)]) if per_class else None
     be = GpuBackend(kb, gamma, n, max_streams=8, scratch_bytes=64 << 20, batch_class=cls,
-                    classes=sorted(set(shape_of.values())) if per_class else None)
-    sched = Scheduler(be.launch, hbm_budget=1 << 30, max_inflight=2, max_batch=5, batch_class=cls)
+                    classes=sorted(set(shape_of.values())) if per_class else None, hash_first=hash_first)
+    sched = Scheduler(be.launch, hbm_budget=1 << 30, max_inflight=2, max_batch=5, batch_class=cls,
+                      hash_first=hash_first)
     reqs = []
     for (kind, s), v in vids.items():
         for t in range(T):
@@ -69,6 +70,7 @@ def test_results_alone_equal_results_in_the_mix(per_class):
     torch.cuda.synchronize()
     assert len(sched.completed) == len(reqs)
     assert any(k == "enc" and size > 1 for k, size in sched.batches), sched.batches
+    assert any(k == "hash" for k, _ in sched.batches) == hash_first
     for r in reqs:
         if r.kind == "enc":
             C, H = alone[r.stream]

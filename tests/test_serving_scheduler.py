@@ -157,3 +157,72 @@ def test_per_stream_inflight_limit():
     be.finish_all()
     s.pump()
     assert be.launched[1][1] == [(0, 2), (0, 3)]
+
+
+def test_hash_first_hashes_beside_the_ordered_stage():
+    be = FakeBackend()
+    s = Scheduler(be.launch, hbm_budget=10**9, max_inflight=4, hash_first=True)
+    s.submit(req(0, 1))                  # frame 1 arrives first: admission waits for frame 0
+    s.pump()
+    assert be.launched == []
+    s.submit(req(0, 0))
+    s.pump()
+    assert be.launched[0][0] == "hash" and be.launched[0][1] == [(0, 0), (0, 1)]
+    s.submit(req(0, 2))
+    s.pump()                             # frame 2 hashes while 0 and 1 are still hashing
+    assert be.launched[1][0] == "hash" and be.launched[1][1] == [(0, 2)]
+    be.launched[1][2].finished = True    # frame 2 hashed first: it waits for 0 and 1
+    s.pump()
+    assert [k for k, _, _ in be.launched] == ["hash", "hash"]
+    be.launched[0][2].finished = True
+    s.pump()
+    assert be.launched[2][0] == "enc" and be.launched[2][1] == [(0, 0), (0, 1), (0, 2)]
+    be.finish_all()
+    s.pump()
+    assert s.idle() and len(s.completed) == 3 and all(r.hashed for r in s.completed)
+
+
+def test_hash_first_charges_the_budget_once():
+    be = FakeBackend()
+    s = Scheduler(be.launch, hbm_budget=100, max_inflight=4, hash_first=True)
+    for k in range(5):
+        s.submit(req(k, 0, nbytes=30))
+    s.pump()
+    assert [len(b) for _, b, _ in be.launched] == [3] and s.inflight_bytes == 90
+    be.launched[0][2].finished = True
+    s.pump()                             # hashed: on to the ordered stage, still holding 90 bytes
+    assert [k for k, _, _ in be.launched] == ["hash", "enc"] and s.inflight_bytes == 90
+    be.finish_all()
+    s.pump()                             # done: the other two are admitted
+    assert s.inflight_bytes == 60 and be.launched[-1][0] == "hash"
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_hash_first_random_arrivals(seed):
+    rng = random.Random(100 + seed)
+    be = FakeBackend()
+    s = Scheduler(be.launch, hbm_budget=150, max_inflight=2, max_batch=5, hash_first=True, max_stream_inflight=3)
+    reqs = [req(st, q, "dec" if st == 5 else "enc", nbytes=rng.randint(1, 50)) for st in range(6) for q in range(10)]
+    order = list(reqs)
+    rng.shuffle(order)
+    for r in order:
+        s.submit(r)
+        s.pump()
+        for _, _, h in be.launched:
+            if rng.random() < 0.4:
+                h.finished = True
+        assert s.inflight_bytes <= 150 or len(s.inflight) == 1
+        assert all(v <= 3 for v in s.stream_inflight.values())
+    while not s.idle():
+        be.finish_all()
+        s.pump()
+    assert len(s.completed) == len(reqs)
+    hashed = {(st, q) for k, items, _ in be.launched if k == "hash" for st, q in items}
+    assert hashed == {(r.stream, r.seq) for r in reqs if r.kind == "enc"}
+    nxt = {}
+    for kind, items, _ in be.launched:
+        if kind == "hash":
+            continue
+        for st, q in items:
+            assert q == nxt.get((kind, st), 0)
+            nxt[(kind, st)] = q + 1
