@@ -8,7 +8,7 @@ hot path over one batch of 300 frames: frame hash (vc_hash_frames), key
 schedule + confusion + XOR (encrypt_frames_hashed), and on a receiver
 context key schedule + inverse confusion (decrypt_frames).  The three run
 as a stream pipeline, the way a sender and a receiver overlap on a live
-link: in each step batch k is hashed, batch k-1 encrypted and batch k-3
+link: in each step batch k is hashed, batch k-2 encrypted and batch k-4
 decrypted, so every step does the full work of one batch.  Frames stay
 resident in HBM; the timed region contains only the library calls.  The
 same work without the pipeline (encrypt_frames then decrypt_frames) is
@@ -68,9 +68,9 @@ def parse():
     ap.add_argument("--parts", type=int, default=3, help="sub-batches per call whose keygen and confusion "
                     "overlap the chain (1 = none)")
     ap.add_argument("--side", type=int, default=3, help="side streams per context for that overlap")
-    ap.add_argument("--slots", type=int, default=3, help="scratch slots per context (one batch each)")
-    ap.add_argument("--lag-enc", type=int, default=1, help="batches between hashing and encrypting a batch")
-    ap.add_argument("--lag-dec", type=int, default=3, help="batches between hashing and decrypting a batch")
+    ap.add_argument("--slots", type=int, default=4, help="scratch slots per context (one batch each)")
+    ap.add_argument("--lag-enc", type=int, default=2, help="batches between hashing and encrypting a batch")
+    ap.add_argument("--lag-dec", type=int, default=4, help="batches between hashing and decrypting a batch")
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="GPU_MAX_HW_QUEUES for this process (0 = HIP default of 4): the benchmark runs 6 streams "
                     "of its own and 4 per context, and streams sharing a hardware queue are serialised")
@@ -508,7 +508,7 @@ def main():
     # Three-stage stream pipeline (a sender that hashes frames as they come
     # and encrypts them as the key chain allows, and a receiver): batch k is
     # hashed while batch k-LE is encrypted and batch k-LD decrypted (defaults
-    # 1 and 3).  Hashing,
+    # 2 and 4).  Hashing,
     # encryption and decryption each alternate between two streams, so that
     # one batch's SHA-256 overlaps the next one's and the key chain of one
     # batch runs while the previous batch's keygen and confusion finish (the

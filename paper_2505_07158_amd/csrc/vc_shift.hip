@@ -52,8 +52,11 @@ __device__ __forceinline__ void map_strip(uint32_t g, uint32_t nstrips, int xcd_
 // ----------------------------------------------------------------------
 // Row pass
 // ----------------------------------------------------------------------
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
 constexpr uint32_t kRowThreads = 256;
-constexpr uint32_t kRowsPerGroup = 2;
+constexpr uint32_t kRowsPerGroup = 4;
+constexpr uint32_t kRowShiftTable = 16 * kRowsPerGroup;  // LDS bytes of the rows' shift amounts
 
 // Four output bytes (pixels 4m..4m+3) of one channel: bits s..s+31 of the
 // channel's bit row, from source pixels q..q+4 (mod w).  `row` is the source
@@ -77,16 +80,54 @@ __device__ __forceinline__ uint32_t shifted4(Ptr row, uint32_t s, uint32_t w) {
     return __builtin_amdgcn_alignbit(b[4], X, t);
 }
 
+// Pixels 4m..4m+3 of all three channels of one row: twelve bytes (pixel k,
+// channel c at byte 3k + c), stored as three dwords when aligned.
+template <typename Ptr>
+__device__ __forceinline__ void shift_group(Ptr row, VC_GLOBAL uint8_t *drow, const uint32_t sh[3], uint32_t m,
+                                            uint32_t w, uint32_t W8, int aligned) {
+    uint32_t o[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        uint32_t s = 32 * m + sh[c];  // 32m < 8w, sh < 8w
+        if (s >= W8) s -= W8;
+        o[c] = shifted4(row + c, s, w);
+    }
+    const uint32_t d0 = (o[0] & 0xFFu) | ((o[1] & 0xFFu) << 8) | ((o[2] & 0xFFu) << 16) | (o[0] << 16 & 0xFF000000u);
+    const uint32_t d1 = ((o[1] >> 8) & 0xFFu) | (o[2] & 0xFF00u) | (o[0] & 0xFF0000u) | ((o[1] << 8) & 0xFF000000u);
+    const uint32_t d2 = ((o[2] >> 16) & 0xFFu) | ((o[0] >> 16) & 0xFF00u) | ((o[1] >> 8) & 0xFF0000u) | (o[2] & 0xFF000000u);
+    if (aligned && 4 * m + 4 <= w) {
+        VC_GLOBAL uint32_t *q4 = reinterpret_cast<VC_GLOBAL uint32_t *>(drow + 12 * m);
+        q4[0] = d0;
+        q4[1] = d1;
+        q4[2] = d2;
+    } else {
+        const uint32_t dw[3] = {d0, d1, d2};
+        const uint32_t nb = 3 * ((w - 4 * m < 4) ? w - 4 * m : 4);
+        for (uint32_t b = 0; b < nb; ++b) drow[12 * m + b] = static_cast<uint8_t>(dw[b >> 2] >> (8 * (b & 3)));
+    }
+}
+
+__device__ __forceinline__ void row_shifts(const VC_GLOBAL uint16_t *D, uint32_t r, uint32_t h, const Geometry &geo,
+                                           bool inv, uint32_t sh[3]) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const uint32_t dh = mod16(D[c * h + r], geo.W8, geo.inv_W8);
+        sh[c] = inv ? dh : (dh ? geo.W8 - dh : 0);
+    }
+}
+
 // One workgroup shifts kRowsPerGroup rows of one frame.  Output byte j of
 // channel c takes bits s..s+7 with s = 8j + sh[c] (mod 8w), sh = 8w - d_h
 // (forward) or d_h (inverse).  A thread produces pixels 4m..4m+3 of all
-// three channels: twelve bytes, three dwords.  With STAGE the source row is
-// first copied to LDS (coalesced); otherwise (rows too long for LDS) the
-// bytes are read from global memory.
+// three channels (twelve bytes) at a time.  With STAGE all rows of the
+// workgroup are first copied to LDS at once (16-byte loads when rows and
+// pointers allow, so that many bytes are in flight), then shifted from
+// there; otherwise (rows too long for LDS) bytes are read from global
+// memory row by row.
 template <bool INV, bool STAGE>
 __global__ __launch_bounds__(kRowThreads) void row_shift(const FrameDesc *__restrict__ desc, uint32_t first,
                                                        uint32_t nframes, Geometry geo, uint32_t groups_per_frame,
-                                                       int aligned) {
+                                                       int aligned, uint32_t lds_row) {
     extern __shared__ __align__(16) uint8_t rowbuf[];
     const uint32_t fl = blockIdx.x / groups_per_frame, grp = blockIdx.x - fl * groups_per_frame;
     if (fl >= nframes) return;
@@ -96,50 +137,50 @@ __global__ __launch_bounds__(kRowThreads) void row_shift(const FrameDesc *__rest
     VC_GLOBAL uint8_t *__restrict__ dst = gmem(INV ? d.out : d.X);
     const VC_GLOBAL uint16_t *__restrict__ D = gmem(d.D);
     const uint32_t ngroups = (w + 3) / 4;
-    for (uint32_t rr = 0; rr < kRowsPerGroup; ++rr) {
-        const uint32_t r = grp * kRowsPerGroup + rr;
-        if (r >= h) break;  // uniform over the workgroup
-        const VC_GLOBAL uint8_t *srow = src + static_cast<uint64_t>(r) * rb;
-        VC_GLOBAL uint8_t *drow = dst + static_cast<uint64_t>(r) * rb;
-        uint32_t sh[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            const uint32_t dh = mod16(D[c * h + r], W8, geo.inv_W8);
-            sh[c] = INV ? dh : (dh ? W8 - dh : 0);
+    const uint32_t r0 = grp * kRowsPerGroup;
+    const uint32_t nr = (h - r0 < kRowsPerGroup) ? h - r0 : kRowsPerGroup;
+    if (STAGE) {
+        // the rows' shift amounts sit after the rows
+        uint32_t(*shS)[3] = reinterpret_cast<uint32_t(*)[3]>(rowbuf + kRowsPerGroup * lds_row);
+        if (threadIdx.x < nr) row_shifts(D, r0 + threadIdx.x, h, geo, INV, shS[threadIdx.x]);
+        const VC_GLOBAL uint8_t *s0 = src + static_cast<uint64_t>(r0) * rb;
+        const bool v16 = aligned && (rb % 16 == 0) && ((reinterpret_cast<uintptr_t>(src) & 15) == 0);
+        if (v16) {
+            // the rows are contiguous: nr * rb / 16 uint4, row k at LDS offset k * lds_row
+            const uint32_t per = rb / 16, n16 = nr * per;
+            for (uint32_t k = threadIdx.x; k < n16; k += kRowThreads) {
+                const uint32_t rr = k / per, e = k - rr * per;
+                reinterpret_cast<u32x4 *>(rowbuf + rr * lds_row)[e] =
+                    reinterpret_cast<const VC_GLOBAL u32x4 *>(s0)[k];
+            }
+        } else if (aligned) {
+            const uint32_t per = rb / 4, n4 = nr * per;
+            for (uint32_t k = threadIdx.x; k < n4; k += kRowThreads) {
+                const uint32_t rr = k / per, e = k - rr * per;
+                reinterpret_cast<uint32_t *>(rowbuf + rr * lds_row)[e] =
+                    reinterpret_cast<const VC_GLOBAL uint32_t *>(s0)[k];
+            }
+        } else {
+            const uint32_t n1 = nr * rb;
+            for (uint32_t k = threadIdx.x; k < n1; k += kRowThreads) {
+                const uint32_t rr = k / rb, e = k - rr * rb;
+                rowbuf[rr * lds_row + e] = s0[k];
+            }
         }
-        if (STAGE) {
-            __syncthreads();  // the previous row's readers are done
-            if (aligned) {
-                const VC_GLOBAL uint32_t *s4 = reinterpret_cast<const VC_GLOBAL uint32_t *>(srow);
-                uint32_t *l4 = reinterpret_cast<uint32_t *>(rowbuf);
-                for (uint32_t k = threadIdx.x; k < rb / 4; k += kRowThreads) l4[k] = s4[k];
-            } else {
-                for (uint32_t k = threadIdx.x; k < rb; k += kRowThreads) rowbuf[k] = srow[k];
-            }
-            __syncthreads();
+        __syncthreads();
+        for (uint32_t k = threadIdx.x; k < nr * ngroups; k += kRowThreads) {
+            const uint32_t rr = k / ngroups, m = k - rr * ngroups;
+            const uint32_t sh[3] = {shS[rr][0], shS[rr][1], shS[rr][2]};
+            shift_group(rowbuf + rr * lds_row, dst + static_cast<uint64_t>(r0 + rr) * rb, sh, m, w, W8, aligned);
         }
-        for (uint32_t m = threadIdx.x; m < ngroups; m += kRowThreads) {
-            uint32_t o[3];
-#pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                uint32_t s = 32 * m + sh[c];  // 32m < 8w, sh < 8w
-                if (s >= W8) s -= W8;
-                o[c] = STAGE ? shifted4(rowbuf + c, s, w) : shifted4(srow + c, s, w);
-            }
-            // byte 3k + c of the twelve is pixel k, channel c
-            const uint32_t d0 = (o[0] & 0xFFu) | ((o[1] & 0xFFu) << 8) | ((o[2] & 0xFFu) << 16) | (o[0] << 16 & 0xFF000000u);
-            const uint32_t d1 = ((o[1] >> 8) & 0xFFu) | (o[2] & 0xFF00u) | (o[0] & 0xFF0000u) | ((o[1] << 8) & 0xFF000000u);
-            const uint32_t d2 = ((o[2] >> 16) & 0xFFu) | ((o[0] >> 16) & 0xFF00u) | ((o[1] >> 8) & 0xFF0000u) | (o[2] & 0xFF000000u);
-            if (aligned && 4 * m + 4 <= w) {
-                VC_GLOBAL uint32_t *q4 = reinterpret_cast<VC_GLOBAL uint32_t *>(drow + 12 * m);
-                q4[0] = d0;
-                q4[1] = d1;
-                q4[2] = d2;
-            } else {
-                const uint32_t dw[3] = {d0, d1, d2};
-                const uint32_t nb = 3 * ((w - 4 * m < 4) ? w - 4 * m : 4);
-                for (uint32_t b = 0; b < nb; ++b) drow[12 * m + b] = static_cast<uint8_t>(dw[b >> 2] >> (8 * (b & 3)));
-            }
+    } else {
+        for (uint32_t rr = 0; rr < nr; ++rr) {
+            const uint32_t r = r0 + rr;
+            uint32_t sh[3];
+            row_shifts(D, r, h, geo, INV, sh);
+            const VC_GLOBAL uint8_t *srow = src + static_cast<uint64_t>(r) * rb;
+            VC_GLOBAL uint8_t *drow = dst + static_cast<uint64_t>(r) * rb;
+            for (uint32_t m = threadIdx.x; m < ngroups; m += kRowThreads) shift_group(srow, drow, sh, m, w, W8, aligned);
         }
     }
 }
@@ -316,13 +357,15 @@ hipError_t launch_row(const FrameDesc *d_desc, uint32_t first, uint32_t count, c
     const uint32_t per_frame = (g.h + kRowsPerGroup - 1) / kRowsPerGroup;
     const uint64_t groups = static_cast<uint64_t>(count) * per_frame;
     if (groups > 0x7FFFFFFFull) return hipErrorInvalidValue;
-    const uint32_t lds = (g.row_bytes + 15u) & ~15u;
+    const uint32_t lds_row = (g.row_bytes + 15u) & ~15u;
+    const uint64_t lds = static_cast<uint64_t>(kRowsPerGroup) * lds_row + kRowShiftTable;
     if (lds <= lds_limit)
-        hipLaunchKernelGGL((row_shift<INV, true>), dim3(static_cast<uint32_t>(groups)), dim3(kRowThreads), lds, s,
-                           d_desc, first, count, g, per_frame, aligned ? 1 : 0);
+        hipLaunchKernelGGL((row_shift<INV, true>), dim3(static_cast<uint32_t>(groups)), dim3(kRowThreads),
+                           static_cast<uint32_t>(lds), s, d_desc, first, count, g, per_frame, aligned ? 1 : 0,
+                           lds_row);
     else
         hipLaunchKernelGGL((row_shift<INV, false>), dim3(static_cast<uint32_t>(groups)), dim3(kRowThreads), 0, s,
-                           d_desc, first, count, g, per_frame, aligned ? 1 : 0);
+                           d_desc, first, count, g, per_frame, aligned ? 1 : 0, lds_row);
     return hipGetLastError();
 }
 
