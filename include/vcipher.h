@@ -70,7 +70,9 @@ typedef struct {
 } vc_key;
 
 /* Shape and position of one frame.  c must be 3; w, h >= 1; w <= 65535,
- * h <= 65535; n <= 3*w*h.  `stream` selects a chain (0 <= stream <
+ * h <= vc_max_frame_height(ctx) (13649 on MI355X with the default two-pass
+ * confusion, whose column pass holds a full-height strip in one workgroup's
+ * LDS); n <= 3*w*h.  `stream` selects a chain (0 <= stream <
  * max_streams of cipher_init); `seq` must equal the stream's next sequence
  * number (0 after cipher_init or cipher_stream_reset), and frames of one
  * stream inside a call appear in increasing seq order. */
@@ -273,6 +275,13 @@ int vc_block_histograms(size_t count, const uint8_t *const *frames, const vc_sha
  * overwritten. */
 int vc_pair_moments(size_t count, const uint8_t *const *frames, const vc_shape *shapes, uint32_t npairs,
                     const uint32_t *positions, uint64_t *moments, void *stream);
+
+/* vc_max_frame_height: the tallest frame the context accepts under its
+ * current confusion form (vc_set_confusion_passes): the column pass, or the
+ * single-pass kernel, keeps a full-height strip of at least 4 pixels in one
+ * workgroup's LDS (Sec. II-C: a column rotation by d_v can move any row to
+ * any row).  Taller frames give VC_EINVAL.  0 for a NULL context. */
+uint32_t vc_max_frame_height(const vc_cipher *ctx);
 
 /* vc_frame_diff: per channel of each pair of frames a[i], b[i] (both of
  * shapes[i]): the number of differing bytes, the sum of |a - b|, the sum of

@@ -240,9 +240,13 @@ bool overlaps(const uint8_t *a, uint64_t la, const uint8_t *b, uint64_t lb) {
 int check_shape(const vc_cipher *ctx, const vc_shape &s, int decrypt, bool uses_n) {
     if (s.c != 3 || s.w < 1 || s.h < 1 || s.w > kMaxDim || s.h > kMaxDim) return VC_EINVAL;
     if (uses_n && ctx->key.n > frame_bytes(s)) return VC_EINVAL;
-    const uint32_t fits = ctx->passes == 2 ? shift_max_strip(s.h, ctx->lds_limit)
-                                           : confuse_max_strip(decrypt, s.h, ctx->lds_limit);
-    if (fits == 0) return VC_EINVAL;
+    // both directions must fit, so that what is encrypted can be decrypted
+    // under the same settings
+    (void)decrypt;
+    const bool fits = ctx->passes == 2 ? shift_max_strip(s.h, ctx->lds_limit) != 0
+                                       : confuse_max_strip(0, s.h, ctx->lds_limit) != 0 &&
+                                             confuse_max_strip(1, s.h, ctx->lds_limit) != 0;
+    if (!fits) return VC_EINVAL;
     return VC_OK;
 }
 
@@ -1229,6 +1233,22 @@ int vc_frame_diff(size_t count, const uint8_t *const *a, const uint8_t *const *b
                               reinterpret_cast<unsigned long long *>(out), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return map_err(e);
+}
+
+uint32_t vc_max_frame_height(const vc_cipher *ctx) {
+    if (!ctx) return 0;
+    // the largest h for which both directions have a strip width that fits
+    auto ok = [&](uint32_t h) {
+        if (ctx->passes == 2) return shift_max_strip(h, ctx->lds_limit) != 0;
+        return confuse_max_strip(0, h, ctx->lds_limit) != 0 && confuse_max_strip(1, h, ctx->lds_limit) != 0;
+    };
+    uint32_t lo = 0, hi = kMaxDim;  // ok(lo) (or lo == 0), answer in [lo, hi]
+    while (lo < hi) {
+        const uint32_t mid = lo + (hi - lo + 1) / 2;
+        if (ok(mid)) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
 int vc_set_confusion_passes(vc_cipher *ctx, uint32_t passes) {

@@ -76,6 +76,8 @@ def _load() -> C.CDLL:
     L.vc_frame_diff.argtypes = [C.c_size_t, C.POINTER(vp), C.POINTER(vp), C.POINTER(VcShape), vp, vp]
     L.vc_autotune.argtypes = [vp, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32),
                               C.POINTER(C.c_uint32)]
+    L.vc_max_frame_height.argtypes = [vp]
+    L.vc_max_frame_height.restype = C.c_uint32
     L.vc_scratch_per_frame.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
     L.vc_scratch_per_frame.restype = C.c_size_t
     L.vc_debug_confuse.argtypes = [vp, C.c_int, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape),
@@ -366,6 +368,10 @@ def vc_frame_diff(a: Sequence[torch.Tensor], b: Sequence[torch.Tensor],
     _check(lib.vc_frame_diff(len(a), _ptrs(a), _ptrs(b), _shapes(a, [0] * len(a), [0] * len(a)),
                              C.c_void_p(out.data_ptr()), C.c_void_p(_stream_handle(stream))), "vc_frame_diff")
     return out
+
+
+def vc_max_frame_height(ctx: int) -> int:
+    return int(lib.vc_max_frame_height(C.c_void_p(ctx)))
 
 
 def vc_scratch_per_frame(w: int, h: int, n: int) -> int:

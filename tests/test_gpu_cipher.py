@@ -324,6 +324,36 @@ def test_large_shapes_parity(w, h, n, frames):
     c.close(); d.close()
 
 
+@pytest.mark.parametrize("passes", [2, 1])
+def test_extreme_shapes(passes):
+    """The tallest frame the context accepts (a 4-pixel-wide strip of it
+    fills the LDS) against the oracle, one row more rejected, and a single
+    row 65535 pixels wide (the row pass then reads global memory)."""
+    dev = require_gpu()
+    Vm = V()
+    kb, n = key_bytes(9), 8
+    c = Vm.Cipher.from_bytes(kb, -1.0, n, max_streams=3)
+    c.passes(passes)
+    hmax = Vm.vc_max_frame_height(c.ctx)
+    assert 1000 < hmax < 65535
+    for s, (h, w) in enumerate([(hmax, 4), (1, 65535), (hmax, 5)]):
+        f = random_frame(h, w, 90 + s)
+        C, H = c.encrypt(to_dev(f[None], dev), streams=[s])
+        Cs, Hs, _ = oracle_stream(kb, -1.0, n, [f])
+        assert to_np(H)[0].tobytes() == Hs[0], (h, w)
+        assert np.array_equal(to_np(C)[0], Cs[0]), (h, w)
+        d = Vm.Cipher.from_bytes(kb, -1.0, n, max_streams=3)
+        d.passes(passes)
+        d._next[s] = 0
+        assert torch.equal(d.decrypt(C, H, streams=[s]), to_dev(f[None], dev)), (h, w)
+        d.close()
+    t = torch.zeros((hmax + 1, 4, 3), dtype=torch.uint8, device=dev)
+    with pytest.raises(Vm.VcError) as e:
+        c.encrypt(t[None], streams=[0])
+    assert e.value.status == Vm.VC_EINVAL
+    c.close()
+
+
 def test_batch_shapes_xcd_split_and_ragged():
     """Batches whose frame count is not a multiple of the 8 XCDs, frames of
     two shapes in one call, and a ragged last strip (w = 100), checked
