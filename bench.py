@@ -44,18 +44,20 @@ def parse():
     ap.add_argument("--workload", choices=["video", "batched", "serving", "robustness"], default="video",
                     help="video: 300 1080p frames per step (default); batched: 48 streams of uneven shapes; "
                     "serving: the request-loop trace; robustness: cropping, noise and key-sensitivity experiments")
-    ap.add_argument("--duration", type=float, default=10.0, help="serving: seconds of arrival trace")
+    ap.add_argument("--duration", type=float, default=60.0, help="serving: seconds of arrival trace")
     ap.add_argument("--hbm-budget-gb", type=float, default=16.0, help="serving: admission budget")
     ap.add_argument("--max-batch", type=int, default=256, help="serving: frames per batch at most")
     ap.add_argument("--plain-frames", type=int, default=400, help="serving: arrivals replayed one frame per launch")
-    ap.add_argument("--inflight", type=int, default=2, help="serving: batches in flight per kind and resolution")
-    ap.add_argument("--inflight-4k", type=int, default=1,
+    ap.add_argument("--inflight", type=int, default=1, help="serving: batches in flight per kind and resolution")
+    ap.add_argument("--inflight-4k", type=int, default=0,
                     help="serving: batches in flight per kind at 3840x2160 (0 = --inflight)")
     ap.add_argument("--hash-first", type=int, default=0,
                     help="serving: 1 = hash each encrypt request on arrival, then chain/keystream/confusion in "
                     "stream order (encrypt_frames_hashed); 0 = one encrypt_frames call per batch")
     ap.add_argument("--serve-parts", type=int, default=1, help="serving: parts per call (vc_set_overlap)")
     ap.add_argument("--serve-side", type=int, default=0, help="serving: side streams per context (vc_set_overlap)")
+    ap.add_argument("--serve-side-1080p", type=int, default=0,
+                    help="serving: side streams of the 1920x1080 contexts (consecutive batches' keygen overlap)")
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--n", type=int, default=32, help="worker count (key material)")
@@ -186,7 +188,8 @@ def run_serving(args) -> None:
         # --serve-side side streams, and one device stream per in-flight batch
         # of each (kind, resolution)
         return cls, GpuBackend(kb, gamma, n, max_streams=S, scratch_bytes=max(budget // len(res_set), 1 << 30),
-                               overlap=(args.serve_parts, args.serve_side, 2),
+                               overlap=lambda kind, c: (args.serve_parts, args.serve_side_1080p
+                                                        if c == (1920, 1080) else args.serve_side, 2),
                                device_streams=lambda kind, c: max(max_inflight(kind, c), 1),
                                classes=res_set, batch_class=cls, hash_first=hash_first)
 
@@ -254,6 +257,8 @@ def run_serving(args) -> None:
         host_launch_s = be.launch_seconds
         be.close()
         lat = np.array([1000.0 * r.latency for r in reqs])
+        wait = np.array([1000.0 * (r.launched - r.arrival) for r in reqs])     # queued on the host
+        serv = np.array([1000.0 * (r.done - r.launched) for r in reqs])        # first launch to completion
         late = np.array([1000.0 * r.latency > 1000.0 / streams[r.stream]["fps"] for r in reqs])
         per_res = {}
         for (w, h) in res_set:
@@ -261,7 +266,11 @@ def run_serving(args) -> None:
             if sel:
                 per_res[f"{w}x{h}"] = {"frames": len(sel), "p50_ms": round(float(np.percentile(lat[sel], 50)), 3),
                                        "p99_ms": round(float(np.percentile(lat[sel], 99)), 3),
-                                       "delay_rate": round(float(late[sel].mean()), 4)}
+                                       "delay_rate": round(float(late[sel].mean()), 4),
+                                       "wait_p50_p99_ms": [round(float(np.percentile(wait[sel], q)), 3)
+                                                           for q in (50, 99)],
+                                       "service_p50_p99_ms": [round(float(np.percentile(serv[sel], q)), 3)
+                                                              for q in (50, 99)]}
         sizes = [b for _, b in sched.batches]
         return {"frames": len(reqs), "wall_s": round(wall, 3), "frames_per_s": round(len(reqs) / wall, 1),
                 "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
@@ -271,7 +280,7 @@ def run_serving(args) -> None:
                 "host_ms_per_batch": round(1000.0 * host_launch_s / max(len(sizes), 1), 3)}
 
     # in flight per kind and resolution: --inflight (--inflight-4k at 3840x2160)
-    # (at 2: 16 device streams + 8 chain streams, within 32 hardware queues)
+    # (at 1: 8 device streams + 8 chain streams, within the hardware queues)
     infl4k = args.inflight_4k or args.inflight
     infl = lambda kind, c: max(1, infl4k if c == (3840, 2160) else args.inflight)
     batched = one_run(trace, args.max_batch, infl, bool(args.hash_first))
@@ -287,7 +296,8 @@ def run_serving(args) -> None:
                        "hbm_budget_gb": args.hbm_budget_gb, "max_batch": args.max_batch,
                        "inflight_batches_per_kind_and_resolution": f"{args.inflight} ({infl4k} at 3840x2160)",
                        "batch_class": "resolution", "hash_first": bool(args.hash_first),
-                       "parts": args.serve_parts, "side_streams": args.serve_side},
+                       "parts": args.serve_parts, "side_streams": args.serve_side,
+                       "side_streams_1080p": args.serve_side_1080p},
             "continuous_batching": batched, "plain_per_frame": plain}
     print(json.dumps(line), flush=True)
 

@@ -117,6 +117,7 @@ struct vc_cipher {
     // priority, created on first use so that idle contexts hold none)
     uint32_t parts = 3;
     uint32_t nside = 3;
+    uint32_t side_base = 0;  // side stream of the next call's first part (rotates across calls)
     uint32_t nslots = 2;
     uint32_t slot_next = 0;
     hipStream_t chain_stream = nullptr;
@@ -609,7 +610,7 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
                                          ctx->key.gamma, ctx->d_flags, cs);
             });
             if (e != hipSuccess) return fail(e);
-            const uint32_t k = static_cast<uint32_t>(ci % nw);
+            const uint32_t k = static_cast<uint32_t>((ctx->side_base + ci) % nw);
             hipStream_t ws = wstream(k);
             if (ws != cs) {
                 e = hipEventRecord(ctx->fork_ev[k], cs);
@@ -636,6 +637,9 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         e = join();
         if (e != hipSuccess) return map_err(e);
         if (uses_scratch) ctx->slot_next = (ctx->slot_next + nspans) % ctx->nslots;
+        // the next call starts on the next side stream, so that the keygen and
+        // confusion of consecutive one-part calls overlap
+        ctx->side_base = static_cast<uint32_t>((ctx->side_base + chunks.size()) % nw);
     } else if (a.op == Op::DebugConfuse) {
         // On the caller's stream; the two-pass intermediate takes scratch
         // slots like any other call.
@@ -1008,6 +1012,7 @@ int vc_set_overlap(vc_cipher *ctx, uint32_t parts, uint32_t side_streams, uint32
     }
     ctx->parts = parts;
     ctx->nside = side_streams;
+    ctx->side_base = 0;
     return VC_OK;
 }
 

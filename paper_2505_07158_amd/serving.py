@@ -246,10 +246,11 @@ class GpuBackend:
     always fall in one class, so each chain lives in one context), so that
     batches of different classes never queue behind each other on a
     context's streams.  Each (kind, class) rotates over ``device_streams``
-    device streams."""
+    device streams.  ``overlap`` (parts, side streams, scratch slots; or a
+    function (kind, class) -> that) configures each context."""
 
     def __init__(self, key32: bytes, gamma: float, n: int, max_streams: int, scratch_bytes: int,
-                 overlap: Optional[Tuple[int, int, int]] = None, device_streams=2,
+                 overlap=None, device_streams=2,
                  classes: Optional[Sequence[object]] = None,
                  batch_class: Optional[Callable[[Request], object]] = None, hash_first: bool = False):
         import torch
@@ -266,8 +267,9 @@ class GpuBackend:
         for cls in (classes if classes else [None]):
             for kind in ("enc", "dec"):
                 c = V.Cipher.from_bytes(key32, gamma, n, max_streams=max_streams, scratch_bytes=scratch_bytes)
-                if overlap:
-                    c.overlap(*overlap)
+                ov = overlap(kind, cls) if callable(overlap) else overlap
+                if ov:
+                    c.overlap(*ov)
                 self.ctx[(kind, cls)] = c
                 ns = device_streams(kind, cls) if callable(device_streams) else device_streams
                 self.streams[(kind, cls)] = [_HipStream(torch) for _ in range(ns)]

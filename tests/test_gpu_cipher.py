@@ -156,7 +156,7 @@ def test_small_scratch_processes_in_chunks():
 
 
 @pytest.mark.parametrize("parts,side,slots", [(1, 0, 1), (4, 2, 2), (3, 1, 3), (7, 4, 2), (64, 3, 4), (2, 0, 2),
-                                               (8, 8, 1)])
+                                               (8, 8, 1), (1, 2, 2), (1, 3, 3), (2, 3, 2)])
 def test_overlap_settings_match_oracle(parts, side, slots):
     """Parts on side streams, chains on the context's chain stream and
     scratch slots never change bytes: 13 frames of one stream against the
@@ -195,6 +195,15 @@ def test_overlap_settings_match_oracle(parts, side, slots):
         ref = Cs[sq] if st == 0 else Co[sq]
         assert np.array_equal(Cn[k], ref), k
     m.close()
+    # one call per frame: consecutive calls start on consecutive side streams
+    c = V().Cipher.from_bytes(kb, -1.0, n)
+    c.overlap(parts, side, slots)
+    outs = [c.encrypt(to_dev(video[t:t + 1], dev)) for t in range(len(video))]
+    for t, (C1, H1) in enumerate(outs):
+        assert to_np(H1)[0].tobytes() == Hs[t], t
+        assert np.array_equal(to_np(C1)[0], Cs[t]), t
+    assert c.status() == 0
+    c.close()
 
 
 @pytest.mark.parametrize("slots", [1, 2, 3])
