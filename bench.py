@@ -818,6 +818,29 @@ def main():
             lat_e.append((b - a) * 1e3)
             lat_d.append((c - b) * 1e3)
 
+    # ---- the plain per-frame path: one call per frame and direction on one
+    # stream, queued without host synchronisation ----
+    plain_pf = None
+    if args.latency_iters > 0:
+        NPF = 30
+        pe = make_cipher(n, max(4 * per_frame_scratch, 64 << 20))
+        pdc = make_cipher(n, max(4 * per_frame_scratch, 64 << 20))
+        cs_ = torch.empty_like(frames[:NPF])
+        ps_ = torch.empty_like(frames[:NPF])
+        hs_ = torch.empty((NPF, 32), dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for k in range(NPF):
+            pe.encrypt(frames[k:k + 1], out=cs_[k:k + 1], hashes=hs_[k:k + 1])
+            pdc.decrypt(cs_[k:k + 1], hs_[k:k + 1], out=ps_[k:k + 1])
+        torch.cuda.synchronize()
+        el_pf = time.perf_counter() - a
+        plain_pf = {"value": round(NPF / el_pf, 1), "unit": "frames/s", "frames": NPF, "calls": 2 * NPF,
+                    "roundtrip_ok": bool(torch.equal(ps_, frames[:NPF])),
+                    "mode": "encrypt_frames then decrypt_frames of one 1920x1080 frame per call, one stream"}
+        pe.close()
+        pdc.close()
+
     # ---- statistics (histogram variance, chi-square, correlation, entropy,
     # local entropy) of one ciphertext batch and of plaintext frames: counts
     # reduced on the GPU, formulas on the host ----
@@ -923,6 +946,7 @@ def main():
                         "mode": f"one {w}x{h} frame per call, host-synchronised"} if lat_e else None),
         "second_row": second,
         "unpipelined": unpiped,
+        "plain_per_frame": plain_pf,
         "statistics": statistics,
         "cpu_baseline": cpu,
         "roundtrip_ok": roundtrip_ok,
