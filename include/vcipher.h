@@ -288,7 +288,9 @@ uint32_t vc_max_frame_height(const vc_cipher *ctx);
  * (a - b)^2 and the number of differing bits -- the counts behind NPCR and
  * UACI (Sec. IV-B, Eqs. 14-16) and behind the PSNR of a frame decrypted
  * after a cropping attack or channel noise (Sec. IV-C).  out: device uint64
- * [count][3 channels][4], overwritten.  VC_EINVAL for bad shapes or NULL
+ * [count][3 channels][4], overwritten.  Like the statistics calls above it
+ * needs no context, synchronises `stream` before returning and allocates
+ * and frees its own device memory.  VC_EINVAL for bad shapes or NULL
  * pointers. */
 int vc_frame_diff(size_t count, const uint8_t *const *a, const uint8_t *const *b, const vc_shape *shapes,
                   uint64_t *out, void *stream);
