@@ -58,8 +58,8 @@ def parse():
     ap.add_argument("--serve-side", type=int, default=0, help="serving: side streams per context (vc_set_overlap)")
     ap.add_argument("--serve-side-1080p", type=int, default=0,
                     help="serving: side streams of the 1920x1080 contexts (consecutive batches' keygen overlap)")
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=32, help="worker count (key material)")
     ap.add_argument("--frames", type=int, default=300)
     ap.add_argument("--width", type=int, default=1920)
