@@ -280,6 +280,34 @@ uint32_t pick_strip(const vc_cipher *ctx, int decrypt, uint32_t w, uint32_t h) {
     return fits;
 }
 
+// The confusion tiling of a shape: the context's fixed tiling, else the
+// autotuned one, else the default strip.  The strip-major layout of the
+// intermediate image uses the same strip width.
+ConfuseTuning choose_tiling(const vc_cipher *ctx, int decrypt, uint32_t w, uint32_t h) {
+    ConfuseTuning t;
+    t.strip = pick_strip(ctx, decrypt, w, h);
+    t.threads = ctx->threads ? ctx->threads : 1024;
+    t.xcd_map = ctx->xcd_map;
+    if (!ctx->strip && !ctx->threads) {
+        auto it = ctx->tuned.find(std::make_tuple(w, h, decrypt, ctx->passes));
+        if (it != ctx->tuned.end()) {
+            t.strip = it->second.first;
+            t.threads = it->second.second;
+        }
+    }
+    return t;
+}
+
+// Strip width of the strip-major intermediate image for a frame of the
+// two-pass confusion with column strips of `strip` pixels, or 0 (row-major):
+// the layout needs whole dwords per row, whole strips per row and rows
+// staged in LDS by the row pass.
+uint32_t layout_strip(const vc_cipher *ctx, uint32_t w, uint32_t strip, bool aligned) {
+    if (!aligned || strip == 0 || w % strip != 0) return 0;
+    if (!shift_rows_staged(w, ctx->lds_limit)) return 0;
+    return strip;
+}
+
 enum class Op { Encrypt, EncryptHashed, Decrypt, Hash, DebugConfuse, DebugKeysched };
 
 struct CallArgs {
@@ -437,9 +465,13 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
             d.D = nullptr;
             d.B = nullptr;
             d.X = nullptr;
+            d.xstrip = 0;
+            d.pad = 0;
             if (two_pass) {
                 d.X = ctx->d_scratch + off;
                 off += align_up(d.L, 256);
+                // strip-major intermediate in the column pass's strips
+                d.xstrip = layout_strip(ctx, s.w, choose_tiling(ctx, dec_kernel, s.w, s.h).strip, aligned_of(f));
             }
             if (keysched_scratch) {
                 const uint64_t ND = 3ull * s.h + 3ull * s.w;
@@ -518,15 +550,7 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
 
     // Confusion + XOR (or its inverse) of one shape group on stream ws.
     auto confuse_group = [&](const Group &g, hipStream_t ws) {
-        tun.strip = pick_strip(ctx, dec_kernel, g.w, g.h);
-        tun.threads = ctx->threads ? ctx->threads : 1024;
-        if (!ctx->strip && !ctx->threads) {
-            auto it = ctx->tuned.find(std::make_tuple(g.w, g.h, dec_kernel, ctx->passes));
-            if (it != ctx->tuned.end()) {
-                tun.strip = it->second.first;
-                tun.threads = it->second.second;
-            }
-        }
+        tun = choose_tiling(ctx, dec_kernel, g.w, g.h);
         if (!two_pass)
             return timed(ctx, dec_kernel ? K_DEC : K_ENC, ws, [&] {
                 return launch_confuse(dec_kernel, d_desc, g.first, g.count, g.w, g.h, g.aligned, tun, ws);
@@ -1070,7 +1094,18 @@ int vc_autotune(vc_cipher *ctx, int decrypt, uint32_t w, uint32_t h, uint32_t fr
                 t.strip = wt;
                 t.threads = nt;
                 t.xcd_map = ctx->xcd_map;
-                // the strip-tiled pass only: the row pass does not depend on the tiling
+                // the strip-tiled pass only (the row pass does not depend on the
+                // tiling), on the layout that the strip implies
+                if (ctx->passes == 2) {
+                    const uint32_t ls = layout_strip(ctx, w, wt, aligned);
+                    if (desc[0].xstrip != ls) {
+                        for (auto &dd : desc) dd.xstrip = ls;
+                        e = hipMemcpyAsync(d_desc, desc.data(), sizeof(FrameDesc) * frames, hipMemcpyHostToDevice,
+                                           st);
+                        if (e == hipSuccess) e = hipStreamSynchronize(st);
+                        if (e != hipSuccess) break;
+                    }
+                }
                 auto run = [&] {
                     if (ctx->passes == 2)
                         return launch_shift(decrypt, decrypt ? 0 : 1, d_desc, 0, frames, w, h, aligned, t,

@@ -28,6 +28,14 @@ struct FrameDesc {
     uint8_t *X;          // 3wh intermediate of the two-pass confusion (S or T)
     uint32_t w, h;
     uint64_t L;          // 3wh
+    // Layout of X: 0 = row-major (the frame's own layout), else strip-major
+    // with strips of that many pixels (WT, a power of two that divides w;
+    // the column pass's strip width): byte c of row r lies in strip
+    // s = c / 3WT at s*h*3WT + r*3WT + c % 3WT, so that a strip's rows are
+    // contiguous and the column pass reads (encrypt) or writes (decrypt)
+    // them linearly.
+    uint32_t xstrip;
+    uint32_t pad;
 };
 
 // One stream's frames inside a part, in sequence order: chain records
@@ -101,6 +109,9 @@ hipError_t confuse_configure(uint32_t lds_limit);
 hipError_t launch_shift(int decrypt, int pass, const FrameDesc *d_desc, uint32_t first, uint32_t count, uint32_t w,
                         uint32_t h, bool aligned, const ConfuseTuning &t, uint32_t lds_limit, hipStream_t s);
 uint32_t shift_max_strip(uint32_t h, uint32_t lds_bytes);
+// True when the row pass stages its rows in LDS for frames of width w (the
+// only form that reads or writes the strip-major intermediate image).
+bool shift_rows_staged(uint32_t w, uint32_t lds_bytes);
 uint32_t shift_col_lds_bytes(uint32_t h, uint32_t strip);
 hipError_t shift_configure(uint32_t lds_limit);
 // Statistics (vc_stats.hip).  hist: count x 3 x 256 (frame) or count x

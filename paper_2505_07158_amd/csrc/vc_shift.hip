@@ -83,7 +83,7 @@ __device__ __forceinline__ uint32_t shifted4(Ptr row, uint32_t s, uint32_t w) {
 // Pixels 4m..4m+3 of all three channels of one row: twelve bytes (pixel k,
 // channel c at byte 3k + c), stored as three dwords when aligned.
 template <typename Ptr>
-__device__ __forceinline__ void shift_group(Ptr row, VC_GLOBAL uint8_t *drow, const uint32_t sh[3], uint32_t m,
+__device__ __forceinline__ void shift_group(Ptr row, VC_GLOBAL uint8_t *piece, const uint32_t sh[3], uint32_t m,
                                             uint32_t w, uint32_t W8, int aligned) {
     uint32_t o[3];
 #pragma unroll
@@ -96,14 +96,14 @@ __device__ __forceinline__ void shift_group(Ptr row, VC_GLOBAL uint8_t *drow, co
     const uint32_t d1 = ((o[1] >> 8) & 0xFFu) | (o[2] & 0xFF00u) | (o[0] & 0xFF0000u) | ((o[1] << 8) & 0xFF000000u);
     const uint32_t d2 = ((o[2] >> 16) & 0xFFu) | ((o[0] >> 16) & 0xFF00u) | ((o[1] >> 8) & 0xFF0000u) | (o[2] & 0xFF000000u);
     if (aligned && 4 * m + 4 <= w) {
-        VC_GLOBAL uint32_t *q4 = reinterpret_cast<VC_GLOBAL uint32_t *>(drow + 12 * m);
+        VC_GLOBAL uint32_t *q4 = reinterpret_cast<VC_GLOBAL uint32_t *>(piece);
         q4[0] = d0;
         q4[1] = d1;
         q4[2] = d2;
     } else {
         const uint32_t dw[3] = {d0, d1, d2};
         const uint32_t nb = 3 * ((w - 4 * m < 4) ? w - 4 * m : 4);
-        for (uint32_t b = 0; b < nb; ++b) drow[12 * m + b] = static_cast<uint8_t>(dw[b >> 2] >> (8 * (b & 3)));
+        for (uint32_t b = 0; b < nb; ++b) piece[b] = static_cast<uint8_t>(dw[b >> 2] >> (8 * (b & 3)));
     }
 }
 
@@ -143,35 +143,79 @@ __global__ __launch_bounds__(kRowThreads) void row_shift(const FrameDesc *__rest
         // the rows' shift amounts sit after the rows
         uint32_t(*shS)[3] = reinterpret_cast<uint32_t(*)[3]>(rowbuf + kRowsPerGroup * lds_row);
         if (threadIdx.x < nr) row_shifts(D, r0 + threadIdx.x, h, geo, INV, shS[threadIdx.x]);
-        const VC_GLOBAL uint8_t *s0 = src + static_cast<uint64_t>(r0) * rb;
-        const bool v16 = aligned && (rb % 16 == 0) && ((reinterpret_cast<uintptr_t>(src) & 15) == 0);
-        if (v16) {
-            // the rows are contiguous: nr * rb / 16 uint4, row k at LDS offset k * lds_row
-            const uint32_t per = rb / 16, n16 = nr * per;
-            for (uint32_t k = threadIdx.x; k < n16; k += kRowThreads) {
-                const uint32_t rr = k / per, e = k - rr * per;
-                reinterpret_cast<u32x4 *>(rowbuf + rr * lds_row)[e] =
-                    reinterpret_cast<const VC_GLOBAL u32x4 *>(s0)[k];
-            }
-        } else if (aligned) {
-            const uint32_t per = rb / 4, n4 = nr * per;
-            for (uint32_t k = threadIdx.x; k < n4; k += kRowThreads) {
-                const uint32_t rr = k / per, e = k - rr * per;
-                reinterpret_cast<uint32_t *>(rowbuf + rr * lds_row)[e] =
-                    reinterpret_cast<const VC_GLOBAL uint32_t *>(s0)[k];
+        // strip-major X (the host sets it only for aligned rows whose width
+        // is a multiple of the strip): decryption reads T from the strips'
+        // runs of nr rows, encryption writes S to them
+        const uint32_t xs = d.xstrip, RSx = 3 * xs;
+        const bool x_sm = xs != 0;
+        if (INV && x_sm) {
+            const uint32_t nstr = w / xs;
+            const uint64_t run0 = static_cast<uint64_t>(r0) * RSx;
+            if (RSx % 16 == 0) {
+                const uint32_t per = RSx / 16, per_strip = nr * per, n16 = nstr * per_strip;
+                for (uint32_t k = threadIdx.x; k < n16; k += kRowThreads) {
+                    const uint32_t st = k / per_strip, within = k - st * per_strip;
+                    const uint32_t rr = within / per, e = within - rr * per;
+                    const uint64_t goff = static_cast<uint64_t>(st) * h * RSx + run0 + static_cast<uint64_t>(within) * 16;
+                    *reinterpret_cast<u32x4 *>(rowbuf + rr * lds_row + st * RSx + 16 * e) =
+                        *reinterpret_cast<const VC_GLOBAL u32x4 *>(src + goff);
+                }
+            } else {
+                const uint32_t per = RSx / 4, per_strip = nr * per, n4 = nstr * per_strip;
+                for (uint32_t k = threadIdx.x; k < n4; k += kRowThreads) {
+                    const uint32_t st = k / per_strip, within = k - st * per_strip;
+                    const uint32_t rr = within / per, e = within - rr * per;
+                    const uint64_t goff = static_cast<uint64_t>(st) * h * RSx + run0 + static_cast<uint64_t>(within) * 4;
+                    *reinterpret_cast<uint32_t *>(rowbuf + rr * lds_row + st * RSx + 4 * e) =
+                        *reinterpret_cast<const VC_GLOBAL uint32_t *>(src + goff);
+                }
             }
         } else {
-            const uint32_t n1 = nr * rb;
-            for (uint32_t k = threadIdx.x; k < n1; k += kRowThreads) {
-                const uint32_t rr = k / rb, e = k - rr * rb;
-                rowbuf[rr * lds_row + e] = s0[k];
+            const VC_GLOBAL uint8_t *s0 = src + static_cast<uint64_t>(r0) * rb;
+            const bool v16 = aligned && (rb % 16 == 0) && ((reinterpret_cast<uintptr_t>(src) & 15) == 0);
+            if (v16) {
+                // the rows are contiguous: nr * rb / 16 uint4, row k at LDS offset k * lds_row
+                const uint32_t per = rb / 16, n16 = nr * per;
+                for (uint32_t k = threadIdx.x; k < n16; k += kRowThreads) {
+                    const uint32_t rr = k / per, e = k - rr * per;
+                    reinterpret_cast<u32x4 *>(rowbuf + rr * lds_row)[e] =
+                        reinterpret_cast<const VC_GLOBAL u32x4 *>(s0)[k];
+                }
+            } else if (aligned) {
+                const uint32_t per = rb / 4, n4 = nr * per;
+                for (uint32_t k = threadIdx.x; k < n4; k += kRowThreads) {
+                    const uint32_t rr = k / per, e = k - rr * per;
+                    reinterpret_cast<uint32_t *>(rowbuf + rr * lds_row)[e] =
+                        reinterpret_cast<const VC_GLOBAL uint32_t *>(s0)[k];
+                }
+            } else {
+                const uint32_t n1 = nr * rb;
+                for (uint32_t k = threadIdx.x; k < n1; k += kRowThreads) {
+                    const uint32_t rr = k / rb, e = k - rr * rb;
+                    rowbuf[rr * lds_row + e] = s0[k];
+                }
             }
         }
         __syncthreads();
-        for (uint32_t k = threadIdx.x; k < nr * ngroups; k += kRowThreads) {
-            const uint32_t rr = k / ngroups, m = k - rr * ngroups;
-            const uint32_t sh[3] = {shS[rr][0], shS[rr][1], shS[rr][2]};
-            shift_group(rowbuf + rr * lds_row, dst + static_cast<uint64_t>(r0 + rr) * rb, sh, m, w, W8, aligned);
+        if (!INV && x_sm) {
+            // lanes in output order: strip, row, 12-byte piece, so that a wave
+            // writes whole runs of nr rows of consecutive strips
+            const uint32_t pps = xs / 4, per_strip = nr * pps, nt = (w / xs) * per_strip;
+            for (uint32_t t = threadIdx.x; t < nt; t += kRowThreads) {
+                const uint32_t st = t / per_strip, within = t - st * per_strip;
+                const uint32_t rr = within / pps, kk = within - rr * pps;
+                const uint32_t sh[3] = {shS[rr][0], shS[rr][1], shS[rr][2]};
+                VC_GLOBAL uint8_t *piece = dst + static_cast<uint64_t>(st) * h * RSx +
+                                           static_cast<uint64_t>(r0 + rr) * RSx + 12 * kk;
+                shift_group(rowbuf + rr * lds_row, piece, sh, st * pps + kk, w, W8, aligned);
+            }
+        } else {
+            for (uint32_t k = threadIdx.x; k < nr * ngroups; k += kRowThreads) {
+                const uint32_t rr = k / ngroups, m = k - rr * ngroups;
+                const uint32_t sh[3] = {shS[rr][0], shS[rr][1], shS[rr][2]};
+                shift_group(rowbuf + rr * lds_row, dst + static_cast<uint64_t>(r0 + rr) * rb + 12 * m, sh, m, w, W8,
+                            aligned);
+            }
         }
     } else {
         for (uint32_t rr = 0; rr < nr; ++rr) {
@@ -180,7 +224,8 @@ __global__ __launch_bounds__(kRowThreads) void row_shift(const FrameDesc *__rest
             row_shifts(D, r, h, geo, INV, sh);
             const VC_GLOBAL uint8_t *srow = src + static_cast<uint64_t>(r) * rb;
             VC_GLOBAL uint8_t *drow = dst + static_cast<uint64_t>(r) * rb;
-            for (uint32_t m = threadIdx.x; m < ngroups; m += kRowThreads) shift_group(srow, drow, sh, m, w, W8, aligned);
+            for (uint32_t m = threadIdx.x; m < ngroups; m += kRowThreads)
+                shift_group(srow, drow + 12 * m, sh, m, w, W8, aligned);
         }
     }
 }
@@ -219,9 +264,20 @@ __global__ __launch_bounds__(NT) void col_shift(const FrameDesc *__restrict__ de
     const uint32_t w = geo.w, h = geo.h, rb = geo.row_bytes;
     const uint32_t j0 = strip * WT;
     const uint32_t wt = (w - j0 < static_cast<uint32_t>(WT)) ? w - j0 : WT;
-    const VC_GLOBAL uint8_t *__restrict__ in = gmem(INV ? d.in : d.X) + 3 * j0;
+    // Each operand is addressed as base + row * stride: row-major (the
+    // strip's columns of each frame row) or, for the intermediate image X,
+    // strip-major (the strip's rows contiguous, stride 3*WT; the host sets
+    // that layout only when its strip width is this kernel's WT and the rows
+    // are aligned).
+    const bool x_sm = d.xstrip != 0;
+    const uint64_t sm_base = static_cast<uint64_t>(strip) * h * RS;
+    const VC_GLOBAL uint8_t *__restrict__ in =
+        INV ? gmem(d.in) + 3 * j0 : gmem(d.X) + (x_sm ? sm_base : 3 * j0);
+    const uint32_t in_stride = (!INV && x_sm) ? RS : rb;
     const VC_GLOBAL uint8_t *__restrict__ Bp = gmem(d.B) + 3 * j0;
-    VC_GLOBAL uint8_t *__restrict__ out = gmem(INV ? d.X : d.out) + 3 * j0;
+    const uint32_t b_stride = rb;
+    VC_GLOBAL uint8_t *__restrict__ out = INV ? gmem(d.X) + (x_sm ? sm_base : 3 * j0) : gmem(d.out) + 3 * j0;
+    const uint32_t out_stride = (INV && x_sm) ? RS : rb;
     const VC_GLOBAL uint16_t *__restrict__ D = gmem(d.D);
     uint8_t *S = smem;
     uint32_t *dvS = reinterpret_cast<uint32_t *>(smem + Lay::dv_off(h));
@@ -235,17 +291,34 @@ __global__ __launch_bounds__(NT) void col_shift(const FrameDesc *__restrict__ de
     const uint32_t g = threadIdx.x % GPR, i0 = threadIdx.x / GPR;
     const bool lane_on = aligned && i0 < RP && g < 3 * wt / 4;
     if (aligned) {
-        // stage: S row i, dword g  <-  in[i][g] (^ B[i][g] when inverse)
-        if (lane_on) {
+        if (!INV && x_sm && (static_cast<uint64_t>(h) * RS) % 16 == 0) {
+            // the strip of S is h*RS contiguous bytes, 16-byte aligned: a
+            // linear copy into LDS by every thread
+            const uint32_t n16 = h * RS / 16;
+            const VC_GLOBAL u32x4 *in4 = reinterpret_cast<const VC_GLOBAL u32x4 *>(in);
+            u32x4 *S4 = reinterpret_cast<u32x4 *>(S);
+            for (uint32_t k0 = threadIdx.x; k0 < n16; k0 += 4 * NT) {
+                u32x4 v[4];
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u)
+                    if (k0 + u * NT < n16) v[u] = in4[k0 + u * NT];
+#pragma unroll
+                for (uint32_t u = 0; u < 4; ++u)
+                    if (k0 + u * NT < n16) S4[k0 + u * NT] = v[u];
+            }
+        } else if (lane_on) {
+            // stage: S row i, dword g  <-  in[i][g] (^ B[i][g] when inverse)
             for (uint32_t base = i0; base < h; base += kUnroll * RP) {
                 uint32_t v[kUnroll], b[kUnroll];
 #pragma unroll
                 for (uint32_t u = 0; u < kUnroll; ++u) {
                     const uint32_t i = base + u * RP;
                     if (i < h) {
-                        const uint64_t off = static_cast<uint64_t>(i) * rb + 4 * g;
-                        v[u] = *reinterpret_cast<const VC_GLOBAL uint32_t *>(in + off);
-                        if (INV) b[u] = *reinterpret_cast<const VC_GLOBAL uint32_t *>(Bp + off);
+                        v[u] = *reinterpret_cast<const VC_GLOBAL uint32_t *>(in + static_cast<uint64_t>(i) * in_stride +
+                                                                              4 * g);
+                        if (INV)
+                            b[u] = *reinterpret_cast<const VC_GLOBAL uint32_t *>(
+                                Bp + static_cast<uint64_t>(i) * b_stride + 4 * g);
                     }
                 }
 #pragma unroll
@@ -266,15 +339,16 @@ __global__ __launch_bounds__(NT) void col_shift(const FrameDesc *__restrict__ de
                 addr[m] = r * RS + p;  // the strip is staged in frame byte order
             }
             const uint32_t stepA = (RP % h) * RS, wrapA = h * RS;
-            const uint64_t offstep = static_cast<uint64_t>(RP) * rb;
-            uint64_t off = static_cast<uint64_t>(i0) * rb + 4 * g;
+            const uint64_t bstep = static_cast<uint64_t>(RP) * b_stride, ostep = static_cast<uint64_t>(RP) * out_stride;
+            uint64_t boff = static_cast<uint64_t>(i0) * b_stride + 4 * g;
+            uint64_t ooff = static_cast<uint64_t>(i0) * out_stride + 4 * g;
             for (uint32_t base = i0; base < h; base += kUnroll * RP) {
                 uint32_t b[kUnroll];
                 if (!INV) {
 #pragma unroll
                     for (uint32_t u = 0; u < kUnroll; ++u)
                         if (base + u * RP < h)
-                            b[u] = *reinterpret_cast<const VC_GLOBAL uint32_t *>(Bp + off + u * offstep);
+                            b[u] = *reinterpret_cast<const VC_GLOBAL uint32_t *>(Bp + boff + u * bstep);
                 }
 #pragma unroll
                 for (uint32_t u = 0; u < kUnroll; ++u) {
@@ -283,7 +357,7 @@ __global__ __launch_bounds__(NT) void col_shift(const FrameDesc *__restrict__ de
                                      (static_cast<uint32_t>(S[addr[2]]) << 16) |
                                      (static_cast<uint32_t>(S[addr[3]]) << 24);
                         if (!INV) v ^= b[u];
-                        *reinterpret_cast<VC_GLOBAL uint32_t *>(out + off + u * offstep) = v;
+                        *reinterpret_cast<VC_GLOBAL uint32_t *>(out + ooff + u * ostep) = v;
 #pragma unroll
                         for (int m = 0; m < 4; ++m) {
                             addr[m] += stepA;
@@ -291,15 +365,16 @@ __global__ __launch_bounds__(NT) void col_shift(const FrameDesc *__restrict__ de
                         }
                     }
                 }
-                off += kUnroll * offstep;
+                boff += kUnroll * bstep;
+                ooff += kUnroll * ostep;
             }
         }
     } else {
         const uint32_t rowlen = 3 * wt;
         for (uint32_t it = threadIdx.x; it < h * rowlen; it += NT) {
             const uint32_t i = it / rowlen, p = it - i * rowlen;
-            const uint64_t off = static_cast<uint64_t>(i) * rb + p;
-            S[i * RS + p] = INV ? (in[off] ^ Bp[off]) : in[off];
+            const uint8_t v = in[static_cast<uint64_t>(i) * in_stride + p];
+            S[i * RS + p] = INV ? (v ^ Bp[static_cast<uint64_t>(i) * b_stride + p]) : v;
         }
         __syncthreads();
         for (uint32_t it = threadIdx.x; it < h * rowlen; it += NT) {
@@ -307,9 +382,9 @@ __global__ __launch_bounds__(NT) void col_shift(const FrameDesc *__restrict__ de
             const uint32_t k = p / 3, c = p - 3 * k;
             const uint32_t dv = dvS[c * WT + k];
             const uint32_t r = (i >= dv) ? i - dv : i + h - dv;
-            const uint64_t off = static_cast<uint64_t>(i) * rb + p;
             const uint8_t v = S[r * RS + p];
-            out[off] = INV ? v : static_cast<uint8_t>(v ^ Bp[off]);
+            out[static_cast<uint64_t>(i) * out_stride + p] =
+                INV ? v : static_cast<uint8_t>(v ^ Bp[static_cast<uint64_t>(i) * b_stride + p]);
         }
     }
 }
@@ -397,6 +472,11 @@ uint32_t shift_col_lds_bytes(uint32_t h, uint32_t strip) {
     case 64: return ColLayout<64>::bytes(h);
     default: return 0xFFFFFFFFu;
     }
+}
+
+bool shift_rows_staged(uint32_t w, uint32_t lds_bytes) {
+    const uint64_t lds_row = (3ull * w + 15u) & ~15ull;
+    return kRowsPerGroup * lds_row + kRowShiftTable <= lds_bytes;
 }
 
 uint32_t shift_max_strip(uint32_t h, uint32_t lds_bytes) {

@@ -216,27 +216,34 @@ class _HipStream:
     all at once; HIP maps streams onto a fixed number of hardware queues
     (GPU_MAX_HW_QUEUES), so with the pool present the library's own streams
     would share queues with active device streams and wait behind their
-    work.  Streams created one by one take the next free queue."""
+    work.  Streams created one by one take the next free queue.
+
+    The streams are never destroyed: torch may still record or query events
+    on a stream after its user is done with it (tensors whose use was
+    recorded on it, completion events), so a closed backend returns its
+    streams to a process-wide pool and the next one reuses them."""
 
     _hip = None
+    _free: List["_HipStream"] = []
 
     def __init__(self, torch):
         import ctypes
         if _HipStream._hip is None:
             _HipStream._hip = ctypes.CDLL("libamdhip64.so")
             _HipStream._hip.hipStreamCreateWithFlags.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.c_uint]
-            _HipStream._hip.hipStreamDestroy.argtypes = [ctypes.c_void_p]
         self.ptr = ctypes.c_void_p()
         rc = _HipStream._hip.hipStreamCreateWithFlags(ctypes.byref(self.ptr), 1)   # hipStreamNonBlocking
         if rc != 0:
             raise RuntimeError(f"hipStreamCreateWithFlags failed ({rc})")
         self.stream = torch.cuda.ExternalStream(self.ptr.value)
 
-    def destroy(self) -> None:
-        if self.ptr.value:
-            self.stream.synchronize()
-            _HipStream._hip.hipStreamDestroy(self.ptr)
-            self.ptr.value = None
+    @classmethod
+    def take(cls, torch) -> "_HipStream":
+        return cls._free.pop() if cls._free else cls(torch)
+
+    def release(self) -> None:
+        self.stream.synchronize()
+        _HipStream._free.append(self)
 
 
 class GpuBackend:
@@ -272,12 +279,12 @@ class GpuBackend:
                     c.overlap(*ov)
                 self.ctx[(kind, cls)] = c
                 ns = device_streams(kind, cls) if callable(device_streams) else device_streams
-                self.streams[(kind, cls)] = [_HipStream(torch) for _ in range(ns)]
+                self.streams[(kind, cls)] = [_HipStream.take(torch) for _ in range(ns)]
                 self.turn[(kind, cls)] = 0
             if hash_first:
                 # "hash" batches run on the sender context of the class
                 ns = device_streams("hash", cls) if callable(device_streams) else device_streams
-                self.streams[("hash", cls)] = [_HipStream(torch) for _ in range(ns)]
+                self.streams[("hash", cls)] = [_HipStream.take(torch) for _ in range(ns)]
                 self.turn[("hash", cls)] = 0
 
     def footprint(self, w: int, h: int) -> int:
@@ -332,6 +339,6 @@ class GpuBackend:
             c.close()
         for ss in self.streams.values():
             for st in ss:
-                st.destroy()
+                st.release()
         self.ctx.clear()
         self.streams.clear()
