@@ -229,27 +229,29 @@ def run_serving(args) -> None:
         # collection over the growing request list would pause the loop)
         gc.collect()
         gc.disable()
-        t0 = time.perf_counter()
-        while i < len(trace) or not sched.idle():
-            now = time.perf_counter() - t0
-            while i < len(trace) and trace[i][0] <= now:
-                ta, s, seq = trace[i]
-                st = streams[s]
-                if st["kind"] == "enc":
-                    frame, hashes, out = pool[s][seq % P], hring[s][seq % R], outs[s][seq % R]
-                else:
-                    frame, hashes = dec_src[s][0][seq % P], dec_src[s][1][seq % P]
-                    out = first[s][seq] if seq < P else outs[s][seq % R]
-                r = Request(stream=s, seq=seq, kind=st["kind"], frame=frame, out=out,
-                            hashes=hashes, nbytes=be.footprint(st["w"], st["h"]), arrival=t0 + ta)
-                reqs.append(r)
-                sched.submit(r)
-                i += 1
-            if not sched.pump():
-                time.sleep(0.0001)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        gc.enable()
+        try:
+            t0 = time.perf_counter()
+            while i < len(trace) or not sched.idle():
+                now = time.perf_counter() - t0
+                while i < len(trace) and trace[i][0] <= now:
+                    ta, s, seq = trace[i]
+                    st = streams[s]
+                    if st["kind"] == "enc":
+                        frame, hashes, out = pool[s][seq % P], hring[s][seq % R], outs[s][seq % R]
+                    else:
+                        frame, hashes = dec_src[s][0][seq % P], dec_src[s][1][seq % P]
+                        out = first[s][seq] if seq < P else outs[s][seq % R]
+                    r = Request(stream=s, seq=seq, kind=st["kind"], frame=frame, out=out,
+                                hashes=hashes, nbytes=be.footprint(st["w"], st["h"]), arrival=t0 + ta)
+                    reqs.append(r)
+                    sched.submit(r)
+                    i += 1
+                if not sched.pump():
+                    time.sleep(0.0001)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        finally:
+            gc.enable()
         # decrypt requests whose ciphertext matches their sequence number
         ok = all(torch.equal(first[r.stream][r.seq], pool[r.stream][r.seq]) for r in reqs
                  if r.kind == "dec" and r.seq < P)
