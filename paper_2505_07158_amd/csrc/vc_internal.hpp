@@ -127,4 +127,14 @@ hipError_t launch_pair_moments(const StatFrame *d_frames, uint32_t count, uint64
 hipError_t launch_frame_diff(const StatFrame *d_a, const StatFrame *d_b, uint32_t count, uint64_t max_bytes,
                              unsigned long long *d_out, hipStream_t s);
 
+// A wave of SHA-256 compression or of the key-stream integrator issues an
+// instruction almost every cycle, so two such waves on one SIMD each run at
+// about half speed while other SIMDs may hold none.  Claiming more than half
+// of a SIMD's 512 registers per lane (256 VGPRs + 8 AGPRs) for every wave of
+// those kernels keeps any two of them off the same SIMD; the bandwidth-bound
+// confusion waves (at most 248 registers) still fit beside one.  Only for
+// kernels of at most four waves per workgroup (one per SIMD of a CU).  The
+// empty asm emits no instruction.
+__device__ __forceinline__ void claim_half_simd() { asm volatile("" ::: "v255", "a7"); }
+
 }  // namespace vc

@@ -217,6 +217,7 @@ __global__ __launch_bounds__(128) void lhcs_keygen(const FrameDesc *__restrict__
                                                    uint32_t n, double gamma, int *__restrict__ flags) {
     __shared__ __align__(16) V4 ring[kKgRing][64];
     __builtin_amdgcn_s_setprio(2);  // latency-bound: ahead of the bandwidth-bound confusion waves
+    claim_half_simd();
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint64_t g = static_cast<uint64_t>(blockIdx.x) * 64 + lane;  // same worker lanes in both waves
     const uint64_t worker = g >> 1;

@@ -323,6 +323,7 @@ __global__ __launch_bounds__(128) void sha256_subframes_2w(const FrameDesc *__re
     __shared__ __align__(16) uint32_t kwbuf[2][64][kKwStride];
     __shared__ uint32_t dig[64][9];
     __builtin_amdgcn_s_setprio(2);  // latency-bound: ahead of the bandwidth-bound confusion waves
+    claim_half_simd();
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const uint32_t lf = lane / n, sub = lane % n;
     const uint32_t f = blockIdx.x * frames_per_group + lf;
