@@ -73,6 +73,9 @@ def parse():
     ap.add_argument("--slots", type=int, default=4, help="scratch slots per context (one batch each)")
     ap.add_argument("--lag-enc", type=int, default=2, help="batches between hashing and encrypting a batch")
     ap.add_argument("--lag-dec", type=int, default=4, help="batches between hashing and decrypting a batch")
+    ap.add_argument("--buffers", type=int, default=0,
+                    help="hash and ciphertext buffer slots (0 = lag-dec + 2); hashing batch k waits until batch "
+                         "k - buffers is decrypted")
     ap.add_argument("--hw-queues", type=int, default=16,
                     help="GPU_MAX_HW_QUEUES for this process (0 = HIP default of 4): the benchmark runs 6 streams "
                     "of its own and 4 per context, and streams sharing a hardware queue are serialised")
@@ -535,11 +538,14 @@ def main():
     # one batch's SHA-256 overlaps the next one's and the key chain of one
     # batch runs while the previous batch's keygen and confusion finish (the
     # library orders the chain and its scratch slots across streams).  Hash
-    # and ciphertext buffers rotate over four slots.
+    # and ciphertext buffers rotate over --buffers slots (lag-dec + 2 by
+    # default).
     LE, LD = args.lag_enc, args.lag_dec
     if not 1 <= LE < LD:
         sys.exit("need 1 <= --lag-enc < --lag-dec")
-    NB = LD + 2
+    NB = args.buffers or LD + 2
+    if NB < LD + 2:
+        sys.exit("need --buffers >= --lag-dec + 2")
     hbuf = [torch.empty((T, 32), dtype=torch.uint8, device=dev) for _ in range(NB)]
     cbuf = [torch.empty_like(frames) for _ in range(NB)]
     plain = [torch.empty_like(frames) for _ in range(2)]
