@@ -94,6 +94,40 @@ def test_rk4_exact_on_linear_subspace():
         assert abs(s[2] - z * R ** m) <= 1e-13 * abs(z)
 
 
+def _rk4_python(s, gamma):
+    """Classical RK4 (step 0.01) of Eq. 1 in plain Python floats: IEEE-754
+    binary64, every operation rounded once, nothing fused.  Written
+    independently of the oracle, in the evaluation order protocol v1 fixes
+    (right-hand sides as printed, the weights summed as ((k1 + 2 k2) + 2 k3) + k4
+    and scaled by h/6)."""
+    def f(x, y, z, w):
+        return (SIGMA * (y - x) + w, (RHO * x - y) - x * z, x * y - BETA * z, gamma * w - y * z)
+    hh, h6 = H_STEP * 0.5, H_STEP / 6.0
+    k1 = f(*s)
+    k2 = f(*[a + hh * b for a, b in zip(s, k1)])
+    k3 = f(*[a + hh * b for a, b in zip(s, k2)])
+    k4 = f(*[a + H_STEP * b for a, b in zip(s, k3)])
+    return [a + h6 * (((b1 + 2.0 * b2) + 2.0 * b3) + b4) for a, b1, b2, b3, b4 in zip(s, k1, k2, k3, k4)]
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_chain_equals_python_floats_bit_for_bit(seed):
+    # Cross-implementation check of the C oracle: Python floats round every
+    # operation exactly like an IEEE-754 FP64 unit with no contraction, so a
+    # 600-step trajectory must agree in every bit.  A fused multiply-add, a
+    # reordered sum or an extended-precision temporary in the C build would
+    # show up here within a few steps (the system is chaotic).
+    rng = np.random.default_rng(seed)
+    for _ in range(4):
+        s = [float(v) for v in rng.uniform(-20.0, 20.0, 4)]
+        gamma = float(rng.uniform(-1.52, -0.06))
+        IR = oracle.chain(np.array(s), gamma, 300)
+        assert IR.shape == (600, 4)
+        for m in range(600):
+            s = _rk4_python(s, gamma)
+            assert [bits(v) for v in s] == [bits(float(v)) for v in IR[m]], (seed, m)
+
+
 @pytest.mark.parametrize("gamma", [-1.52, -0.8, -0.06])
 def test_trajectories_stay_bounded(gamma):
     rng = np.random.default_rng(int(-gamma * 100))
