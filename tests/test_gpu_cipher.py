@@ -142,6 +142,36 @@ def test_multistream_mixed_batch_equals_streams_alone():
     mixed.close(); dec.close()
 
 
+def test_more_issue_bound_waves_than_simds():
+    """3,000 small frames of 12 interleaved streams at n = 32 in one call: the
+    SHA-256 launch then holds 3,000 waves and every keygen part about 2,000,
+    each wave claiming more than half of a SIMD's registers, against 1,024
+    SIMDs, so most workgroups wait for a free SIMD.  Every stream must still
+    equal the oracle, and the batch must decrypt back."""
+    dev = require_gpu()
+    kb = key_bytes(12)
+    S, T, n = 12, 250, 32
+    vids = {s: [random_frame(16, 24, seed=100000 + 1000 * s + t) for t in range(T)] for s in range(S)}
+    order = [(s, t) for t in range(T) for s in range(S)]
+    enc = V().Cipher.from_bytes(kb, -1.0, n, max_streams=S)
+    outs, H = enc.encrypt([to_dev(vids[s][t], dev) for s, t in order], streams=[s for s, _ in order])
+    outs = [to_np(o) for o in outs]
+    Hn = to_np(H)
+    assert enc.status() == 0
+    for s in range(S):
+        Cs, Hs, _ = oracle_stream(kb, -1.0, n, vids[s])
+        for t in range(T):
+            k = t * S + s  # position of (s, t) in order
+            assert np.array_equal(outs[k], Cs[t]), (s, t)
+            assert Hn[k].tobytes() == Hs[t], (s, t)
+    dec = V().Cipher.from_bytes(kb, -1.0, n, max_streams=S)
+    P = dec.decrypt([to_dev(o, dev) for o in outs], H, streams=[s for s, _ in order])
+    for (s, t), p in zip(order, P):
+        assert np.array_equal(to_np(p), vids[s][t]), (s, t)
+    assert dec.status() == 0
+    enc.close(); dec.close()
+
+
 def test_small_scratch_processes_in_chunks():
     dev = require_gpu()
     kb = key_bytes(4)
