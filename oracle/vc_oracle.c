@@ -19,13 +19,18 @@
  *                                      sub-case, convergence order)
  *   reconstruction ................... pinned by closed-form invariants
  *                                      (involution, bit positions, H = 0)
- *   worker init / byte stream / D,B .. readings R6-R9; pinned only by
+ *   worker init / byte stream / D,B .. readings R6-R9; pinned by
  *                                      invariants (zero stream for equal
- *                                      LHCS pairs, byte accounting).  Parity
- *                                      against the authors' program is
- *                                      unpinned: their code is not available.
- *   confusion + XOR and inverse ...... pinned (literal Algs. 3-7, numpy
- *                                      roll/packbits, bijection probes)
+ *                                      LHCS pairs, byte accounting) and bit
+ *                                      for bit by a separate pure-Python
+ *                                      statement of the same readings,
+ *                                      which catches planted mistakes.
+ *                                      Against the authors' program the
+ *                                      readings stay unpinned: their code
+ *                                      is not available.
+ *   confusion + XOR and inverse ...... pinned (bit-matrix form of Eqs. 2-3
+ *                                      and Algs. 3-7, numpy roll/packbits,
+ *                                      bijection probes)
  */
 #include "vc_oracle.h"
 
@@ -383,106 +388,100 @@ void vco_confuse_dec(const uint8_t *C, uint32_t w, uint32_t h,
             }
 }
 
-/* Literal form: one byte per bit, M[c][i][x], x in [0, 8w). */
+/* Bit-matrix form.  Each channel c of a frame is the h x 8w bit matrix of
+ * Alg. 3: entry (i, 8j + k) is bit k (least significant first) of byte
+ * (i, j, c); Alg. 7 reads a byte back as the sum of its eight entries times
+ * 2^k.  Eq. 2 and Eq. 3 are then permutations of whole matrices, written
+ * here in gather form (each destination entry fetched through the inverse
+ * index), one full matrix per stage, independent of the per-byte closed
+ * form above.  One byte per bit: M[(c*h + i)*8w + x]. */
 #define BIT(M, w, h, c, i, x) ((M)[((uint64_t)(c) * (h) + (i)) * (8ull * (w)) + (x)])
 
+/* Alg. 3: the bit matrices of a frame. */
+static void to_bits(const uint8_t *F, uint32_t w, uint32_t h, uint8_t *M)
+{
+    for (uint32_t c = 0; c < 3; ++c)
+        for (uint32_t i = 0; i < h; ++i)
+            for (uint64_t x = 0; x < 8ull * w; ++x)
+                BIT(M, w, h, c, i, x) = (uint8_t)((PIX(F, w, i, x / 8, c) >> (x % 8)) & 1u);
+}
+
+/* Alg. 7: bytes from bit matrices. */
+static void from_bits(const uint8_t *M, uint32_t w, uint32_t h, uint8_t *F)
+{
+    for (uint32_t c = 0; c < 3; ++c)
+        for (uint32_t i = 0; i < h; ++i)
+            for (uint32_t j = 0; j < w; ++j) {
+                uint32_t sum = 0;
+                for (uint32_t k = 0; k < 8; ++k) sum += (uint32_t)BIT(M, w, h, c, i, 8ull * j + k) << k;
+                PIX(F, w, i, j, c) = (uint8_t)sum;
+            }
+}
+
+/* Eq. 2 on every bit row r of channel c, by d_h(c, r): the entry at column
+ * x moves to column (x + d_h) mod 8w, so destination column x holds source
+ * column (x - d_h) mod 8w.  inverse != 0 applies the inverse permutation. */
+static void rotate_rows(const uint8_t *src, uint8_t *dst, uint32_t w, uint32_t h, const uint16_t *D, int inverse)
+{
+    const uint64_t W8 = 8ull * w;
+    for (uint32_t c = 0; c < 3; ++c)
+        for (uint32_t r = 0; r < h; ++r) {
+            const uint64_t d = D[(uint64_t)c * h + r] % W8;
+            const uint64_t back = inverse ? d : W8 - d;   /* destination x reads source x + back */
+            for (uint64_t x = 0; x < W8; ++x) BIT(dst, w, h, c, r, x) = BIT(src, w, h, c, r, (x + back) % W8);
+        }
+}
+
+/* Eq. 3 on every bit column x of channel c, by d_v(c, x / 8) (one distance
+ * per pixel column [R10]): the entry at row i moves to row (i + d_v) mod h. */
+static void rotate_columns(const uint8_t *src, uint8_t *dst, uint32_t w, uint32_t h, const uint16_t *D, int inverse)
+{
+    const uint64_t W8 = 8ull * w;
+    for (uint32_t c = 0; c < 3; ++c)
+        for (uint64_t x = 0; x < W8; ++x) {
+            const uint64_t d = D[3ull * h + (uint64_t)c * w + x / 8] % h;
+            const uint64_t back = inverse ? d : h - d;
+            for (uint32_t i = 0; i < h; ++i) BIT(dst, w, h, c, i, x) = BIT(src, w, h, c, (i + back) % h, x);
+        }
+}
+
+/* Alg. 6: xor with the bit matrices of B, in place. */
+static void xor_bits(uint8_t *M, uint32_t w, uint32_t h, const uint8_t *B, uint8_t *scratch)
+{
+    to_bits(B, w, h, scratch);
+    for (uint64_t q = 0; q < 3ull * h * 8ull * w; ++q) M[q] ^= scratch[q];
+}
+
+/* Encryption on the bit matrices: Alg. 3, Eq. 2 (Alg. 4), Eq. 3 (Alg. 5),
+ * Alg. 6, Alg. 7, read as a dataflow chain [R11]. */
 int vco_confuse_enc_literal(const uint8_t *P, uint32_t w, uint32_t h,
                             const uint16_t *D, const uint8_t *B, uint8_t *C)
 {
-    const uint64_t W8 = 8ull * w, cells = 3ull * h * W8;
-    uint8_t *Mt = (uint8_t *)calloc(cells, 1), *Me = (uint8_t *)calloc(cells, 1);
-    if (!Mt || !Me) { free(Mt); free(Me); return -1; }
-    /* Alg. 3: bit k of pixel (i,j,c) -> M_t(i, 8j + k). */
-    for (uint32_t c = 0; c < 3; ++c)
-        for (uint32_t i = 0; i < h; ++i)
-            for (uint32_t j = 0; j < w; ++j) {
-                uint8_t v = PIX(P, w, i, j, c);
-                for (int k = 0; k < 8; ++k) { BIT(Mt, w, h, c, i, 8 * j + k) = v & 1; v >>= 1; }
-            }
-    /* Alg. 4 / Eq. 2: M_e(i, (8j+k + (d_h mod 8w)) mod 8w) = M_t(i, 8j+k). */
-    for (uint32_t c = 0; c < 3; ++c)
-        for (uint32_t i = 0; i < h; ++i) {
-            uint64_t dh = D[(uint64_t)c * h + i];
-            for (uint64_t x = 0; x < W8; ++x)
-                BIT(Me, w, h, c, i, (x + dh % W8) % W8) = BIT(Mt, w, h, c, i, x);
-        }
-    memcpy(Mt, Me, cells); /* M_t <- M_e (the dataflow reading of Alg. 1) [R11] */
-    /* Alg. 5 / Eq. 3: M_e((i + (d_v mod h)) mod h, 8j+k) = M_t(i, 8j+k). */
-    for (uint32_t c = 0; c < 3; ++c)
-        for (uint32_t i = 0; i < h; ++i)
-            for (uint64_t x = 0; x < W8; ++x) {
-                uint64_t dv = D[3ull * h + (uint64_t)c * w + x / 8];
-                BIT(Me, w, h, c, (i + dv % h) % h, x) = BIT(Mt, w, h, c, i, x);
-            }
-    memcpy(Mt, Me, cells);
-    /* Alg. 6: xor with the bits of b = B(i,j,c), least significant first. */
-    for (uint32_t c = 0; c < 3; ++c)
-        for (uint32_t i = 0; i < h; ++i)
-            for (uint32_t j = 0; j < w; ++j) {
-                uint8_t b = PIX(B, w, i, j, c);
-                for (int k = 0; k < 8; ++k) {
-                    BIT(Me, w, h, c, i, 8 * j + k) = BIT(Mt, w, h, c, i, 8 * j + k) ^ (b & 1);
-                    b >>= 1;
-                }
-            }
-    memcpy(Mt, Me, cells);
-    /* Alg. 7: F_e(i,j) accumulates bits k = 7..0, shifting left between them
-     * (starting from zero [R13]). */
-    for (uint32_t c = 0; c < 3; ++c)
-        for (uint32_t i = 0; i < h; ++i)
-            for (uint32_t j = 0; j < w; ++j) {
-                uint32_t f = 0;
-                for (int k = 7; k >= 0; --k) {
-                    f |= BIT(Mt, w, h, c, i, 8 * j + k);
-                    if (k != 0) f <<= 1;
-                }
-                PIX(C, w, i, j, c) = (uint8_t)f;
-            }
-    free(Mt);
-    free(Me);
+    const uint64_t cells = 3ull * h * 8ull * w;
+    uint8_t *M0 = (uint8_t *)malloc(cells), *M1 = (uint8_t *)malloc(cells), *M2 = (uint8_t *)malloc(cells);
+    if (!M0 || !M1 || !M2) { free(M0); free(M1); free(M2); return -1; }
+    to_bits(P, w, h, M0);
+    rotate_rows(M0, M1, w, h, D, 0);
+    rotate_columns(M1, M2, w, h, D, 0);
+    xor_bits(M2, w, h, B, M0);
+    from_bits(M2, w, h, C);
+    free(M0); free(M1); free(M2);
     return 0;
 }
 
-/* Literal inverse: each of Algs. 7, 6, 5, 4, 3 undone in reverse order. */
+/* Decryption on the bit matrices: the same stages undone in reverse order. */
 int vco_confuse_dec_literal(const uint8_t *C, uint32_t w, uint32_t h,
                             const uint16_t *D, const uint8_t *B, uint8_t *P)
 {
-    const uint64_t W8 = 8ull * w, cells = 3ull * h * W8;
-    uint8_t *Mt = (uint8_t *)calloc(cells, 1), *Me = (uint8_t *)calloc(cells, 1);
-    if (!Mt || !Me) { free(Mt); free(Me); return -1; }
-    for (uint32_t c = 0; c < 3; ++c)            /* undo Alg. 7 */
-        for (uint32_t i = 0; i < h; ++i)
-            for (uint32_t j = 0; j < w; ++j) {
-                uint8_t v = PIX(C, w, i, j, c);
-                for (int k = 0; k < 8; ++k) { BIT(Mt, w, h, c, i, 8 * j + k) = v & 1; v >>= 1; }
-            }
-    for (uint32_t c = 0; c < 3; ++c)            /* undo Alg. 6 */
-        for (uint32_t i = 0; i < h; ++i)
-            for (uint32_t j = 0; j < w; ++j) {
-                uint8_t b = PIX(B, w, i, j, c);
-                for (int k = 0; k < 8; ++k) { BIT(Mt, w, h, c, i, 8 * j + k) ^= (b & 1); b >>= 1; }
-            }
-    for (uint32_t c = 0; c < 3; ++c)            /* undo Alg. 5 */
-        for (uint32_t i = 0; i < h; ++i)
-            for (uint64_t x = 0; x < W8; ++x) {
-                uint64_t dv = D[3ull * h + (uint64_t)c * w + x / 8];
-                BIT(Me, w, h, c, i, x) = BIT(Mt, w, h, c, (i + dv % h) % h, x);
-            }
-    for (uint32_t c = 0; c < 3; ++c)            /* undo Alg. 4 */
-        for (uint32_t i = 0; i < h; ++i) {
-            uint64_t dh = D[(uint64_t)c * h + i];
-            for (uint64_t x = 0; x < W8; ++x)
-                BIT(Mt, w, h, c, i, x) = BIT(Me, w, h, c, i, (x + dh % W8) % W8);
-        }
-    for (uint32_t c = 0; c < 3; ++c)            /* undo Alg. 3 */
-        for (uint32_t i = 0; i < h; ++i)
-            for (uint32_t j = 0; j < w; ++j) {
-                uint32_t f = 0;
-                for (int k = 0; k < 8; ++k) f |= (uint32_t)BIT(Mt, w, h, c, i, 8 * j + k) << k;
-                PIX(P, w, i, j, c) = (uint8_t)f;
-            }
-    free(Mt);
-    free(Me);
+    const uint64_t cells = 3ull * h * 8ull * w;
+    uint8_t *M0 = (uint8_t *)malloc(cells), *M1 = (uint8_t *)malloc(cells), *M2 = (uint8_t *)malloc(cells);
+    if (!M0 || !M1 || !M2) { free(M0); free(M1); free(M2); return -1; }
+    to_bits(C, w, h, M2);
+    xor_bits(M2, w, h, B, M0);
+    rotate_columns(M2, M1, w, h, D, 1);
+    rotate_rows(M1, M0, w, h, D, 1);
+    from_bits(M0, w, h, P);
+    free(M0); free(M1); free(M2);
     return 0;
 }
 

@@ -65,9 +65,9 @@ void vco_confuse_enc(const uint8_t *P, uint32_t w, uint32_t h,
 /* Its exact inverse. */
 void vco_confuse_dec(const uint8_t *C, uint32_t w, uint32_t h,
                      const uint16_t *D, const uint8_t *B, uint8_t *P);
-/* The same two transforms computed literally on 8w x h bit matrices,
- * step by step as Algs. 3-7 describe (slow; small frames). Return -1 on
- * allocation failure. */
+/* The same two transforms computed on the 8w x h bit matrices of Alg. 3,
+ * stage by stage (Alg. 3, Eq. 2, Eq. 3, Alg. 6, Alg. 7), each permutation
+ * in gather form (slow; small frames). Return -1 on allocation failure. */
 int vco_confuse_enc_literal(const uint8_t *P, uint32_t w, uint32_t h,
                             const uint16_t *D, const uint8_t *B, uint8_t *C);
 int vco_confuse_dec_literal(const uint8_t *C, uint32_t w, uint32_t h,
