@@ -444,7 +444,7 @@ def run_batched(args) -> None:
     for (w, h) in sorted(set(shapes)):
         se_, te_ = enc.autotune(w, h, frames=F * 16, decrypt=False)
         sd_, td_ = dec.autotune(w, h, frames=F * 16, decrypt=True)
-        tuned[f"{w}x{h}"] = {"encrypt": {"strip_px": se_, "threads": te_}, "decrypt": {"strip_px": sd_, "threads": td_}}
+        tuned[f"{w}x{h}"] = {"encrypt": {"strip_bytes": se_, "threads": te_}, "decrypt": {"strip_bytes": sd_, "threads": td_}}
     torch.cuda.synchronize()
     step(0)                     # batch 0, kept for the plain-path comparison
     torch.cuda.synchronize()

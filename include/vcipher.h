@@ -70,9 +70,9 @@ typedef struct {
 } vc_key;
 
 /* Shape and position of one frame.  c must be 3; w, h >= 1; w <= 65535,
- * h <= vc_max_frame_height(ctx) (13649 on MI355X with the default two-pass
- * confusion, whose column pass holds a full-height strip in one workgroup's
- * LDS); n <= 3*w*h.  `stream` selects a chain (0 <= stream <
+ * h <= vc_max_frame_height(ctx) (40956 on MI355X with the default two-pass
+ * confusion, whose column pass holds a full-height strip of at least 4
+ * bytes per row in one workgroup's LDS); n <= 3*w*h.  `stream` selects a chain (0 <= stream <
  * max_streams of cipher_init); `seq` must equal the stream's next sequence
  * number (0 after cipher_init or cipher_stream_reset), and frames of one
  * stream inside a call appear in increasing seq order. */
@@ -212,8 +212,8 @@ size_t vc_scratch_per_frame(uint32_t w, uint32_t h, uint32_t n);
 
 /* Autotuner: time the strip-tiled confusion pass (the column pass of the
  * two-pass form, or the single pass) for w x h frames, `frames` per launch
- * (1..4096), over every strip width the LDS holds and 256/512/1024
- * threads, on buffers it allocates and frees itself (contents arbitrary:
+ * (1..4096), over every strip width the LDS holds (see vc_set_tuning) and
+ * 256/512/1024 threads, on buffers it allocates and frees itself (contents arbitrary:
  * the kernels are data-oblivious), and remember the fastest for this
  * shape, direction (decrypt 0/1) and pass count.  Later calls use it unless
  * vc_set_tuning fixed a tiling.  Writes the choice to *strip_out and
@@ -222,10 +222,16 @@ size_t vc_scratch_per_frame(uint32_t w, uint32_t h, uint32_t n);
 int vc_autotune(vc_cipher *ctx, int decrypt, uint32_t w, uint32_t h, uint32_t frames, uint32_t *strip_out,
                 uint32_t *threads_out);
 
-/* Strip width (pixels: 4, 8, 16, 32 or 64; 0 = automatic) and
- * threads per workgroup (256, 512 or 1024; 0 = automatic) of the
- * confusion kernels, and whether workgroups are mapped so that all strips
- * of one frame run on one XCD.  Tuning never changes output bytes. */
+/* Strip width of the confusion kernels (0 = automatic; else a power of two
+ * from 4 to 128): for the two-pass form, bytes of a row per column-pass
+ * strip (the column rotation of Eq. 3 moves each byte column on its own, so
+ * strips need not hold whole pixels; 128 bytes = one cache line); for the
+ * single-pass form, pixels (at most 64).  A width the LDS cannot hold for a
+ * frame's height, or wider than the form allows, falls back to the
+ * automatic choice.  threads per workgroup: 256, 512 or 1024 (0 =
+ * automatic).  xcd_map: map workgroups so that all strips of one frame run
+ * on one XCD.  Tuning never changes output bytes.  VC_EINVAL for other
+ * values. */
 int vc_set_tuning(vc_cipher *ctx, uint32_t strip_width, uint32_t threads, int xcd_map);
 
 /* Testing entry point: run the confusion + XOR kernels (decrypt = 0) or
@@ -243,6 +249,18 @@ int vc_debug_confuse(vc_cipher *ctx, int decrypt, size_t count, const uint8_t *c
 int vc_debug_keysched(vc_cipher *ctx, size_t count, const vc_shape *shapes,
                       const uint8_t *hashes, double *const *IR, uint16_t *const *D,
                       uint8_t *const *B, void *stream);
+
+/* Testing entry point: the keystream generation of Sec. II-B (Alg. 2)
+ * alone.  For each frame, the n worker LHCS pairs are seeded from the
+ * caller's LHCS_m iterates IR[f] (device, 2n x 4 doubles: x, y, z, w of
+ * iterations 1..2n) and write distances D[f] (device, 3h+3w uint16) and
+ * keystream B[f] (device, L bytes); only w, h, c of shapes are read, and no
+ * chain state is read or changed.  A worker trajectory that leaves the
+ * finite range raises the device flag that cipher_status reports as
+ * VC_ENONFINITE (the outputs are then meaningless but every kernel ends
+ * normally).  Same kernel as encrypt_frames. */
+int vc_debug_keygen(vc_cipher *ctx, size_t count, const vc_shape *shapes, const double *const *IR,
+                    uint16_t *const *D, uint8_t *const *B, void *stream);
 
 /* ---- Statistics of Sec. III (integer reductions; formulas on the host) ----
  * These need no context; each is synchronous (it synchronises `stream`
@@ -277,9 +295,9 @@ int vc_pair_moments(size_t count, const uint8_t *const *frames, const vc_shape *
                     const uint32_t *positions, uint64_t *moments, void *stream);
 
 /* vc_max_frame_height: the tallest frame the context accepts under its
- * current confusion form (vc_set_confusion_passes): the column pass, or the
- * single-pass kernel, keeps a full-height strip of at least 4 pixels in one
- * workgroup's LDS (Sec. II-C: a column rotation by d_v can move any row to
+ * current confusion form (vc_set_confusion_passes): the column pass keeps a
+ * full-height strip of at least 4 bytes per row, the single-pass kernel one
+ * of at least 4 pixels, in one workgroup's LDS (Sec. II-C: a column rotation by d_v can move any row to
  * any row).  Taller frames give VC_EINVAL.  0 for a NULL context. */
 uint32_t vc_max_frame_height(const vc_cipher *ctx);
 

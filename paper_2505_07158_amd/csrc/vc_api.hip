@@ -77,7 +77,7 @@ struct DeviceGuard {
 
 struct Group {  // frames [first, first + count) of the descriptor array share a shape
     uint32_t first, count, w, h;
-    bool aligned;
+    int align;  // alignment class every frame of the group meets (launch_shift)
 };
 
 struct Chunk {  // one part of a scratch span
@@ -254,17 +254,22 @@ int check_shape(const vc_cipher *ctx, const vc_shape &s, int decrypt, bool uses_
 uint32_t pick_strip(const vc_cipher *ctx, int decrypt, uint32_t w, uint32_t h) {
     const uint32_t wcap = std::max<uint32_t>(4, (w + 3) / 4 * 4);
     if (ctx->passes == 2) {
-        if (ctx->strip && ctx->strip <= wcap && shift_col_lds_bytes(h, ctx->strip) <= ctx->lds_limit)
+        // strips of bytes: a strip wider than the row is never needed
+        const uint32_t bcap = std::max<uint32_t>(4, 1u << (32 - __builtin_clz(std::max<uint32_t>(3 * w, 2) - 1)));
+        if (ctx->strip && ctx->strip <= bcap && shift_col_lds_bytes(h, ctx->strip) <= ctx->lds_limit)
             return ctx->strip;
-        // widest strip that leaves room for two column-pass workgroups per CU
+        // the widest strip (up to one 128-byte line) that leaves room for two
+        // column-pass workgroups per CU, else the widest that fits: measured
+        // on MI355X, the column pass then shares CUs best with the
+        // latency-bound SHA-256 and keystream waves of a pipelined stream
         uint32_t half = 0, fits = 0;
-        for (uint32_t wt = 4; wt <= 64 && wt <= wcap; wt *= 2) {
-            if (shift_col_lds_bytes(h, wt) <= ctx->lds_limit / 2) half = wt;
-            if (shift_col_lds_bytes(h, wt) <= ctx->lds_limit) fits = wt;
+        for (uint32_t sb = 4; sb <= 128 && sb <= bcap; sb *= 2) {
+            if (shift_col_lds_bytes(h, sb) <= ctx->lds_limit / 2) half = sb;
+            if (shift_col_lds_bytes(h, sb) <= ctx->lds_limit) fits = sb;
         }
         return half ? half : fits;
     }
-    if (ctx->strip) {
+    if (ctx->strip && ctx->strip <= 64) {
         if (ctx->strip <= wcap && confuse_lds_bytes(decrypt, h, ctx->strip) <= ctx->lds_limit)
             return ctx->strip;
     }
@@ -298,17 +303,8 @@ ConfuseTuning choose_tiling(const vc_cipher *ctx, int decrypt, uint32_t w, uint3
     return t;
 }
 
-// Strip width of the strip-major intermediate image for a frame of the
-// two-pass confusion with column strips of `strip` pixels, or 0 (row-major):
-// the layout needs whole dwords per row, whole strips per row and rows
-// staged in LDS by the row pass.
-uint32_t layout_strip(const vc_cipher *ctx, uint32_t w, uint32_t strip, bool aligned) {
-    if (!aligned || strip == 0 || w % strip != 0) return 0;
-    if (!shift_rows_staged(w, ctx->lds_limit)) return 0;
-    return strip;
-}
 
-enum class Op { Encrypt, EncryptHashed, Decrypt, Hash, DebugConfuse, DebugKeysched };
+enum class Op { Encrypt, EncryptHashed, Decrypt, Hash, DebugConfuse, DebugKeysched, DebugKeygen };
 
 struct CallArgs {
     Op op;
@@ -320,7 +316,7 @@ struct CallArgs {
     uint8_t *const *out;
     const uint16_t *const *dbgD;  // debug confuse inputs
     const uint8_t *const *dbgB;
-    double *const *kIR;           // debug keysched outputs
+    double *const *kIR;           // debug keysched outputs (debug keygen: input)
     uint16_t *const *kD;
     uint8_t *const *kB;
     int decrypt;                  // for DebugConfuse
@@ -363,12 +359,13 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         int rc = check_shape(ctx, s, dec_kernel, a.op != Op::DebugConfuse);
         if (rc) return rc;
         const uint64_t L = frame_bytes(s);
-        if (a.op != Op::DebugKeysched && !a.in[f]) return VC_EINVAL;
+        if (a.op != Op::DebugKeysched && a.op != Op::DebugKeygen && !a.in[f]) return VC_EINVAL;
         if ((encrypting || a.op == Op::Decrypt || a.op == Op::DebugConfuse) && !a.out[f]) return VC_EINVAL;
         if ((encrypting || a.op == Op::DebugConfuse || a.op == Op::Decrypt) && overlaps(a.in[f], L, a.out[f], L))
             return VC_EINVAL;
         if (a.op == Op::DebugConfuse && (!a.dbgD[f] || !a.dbgB[f])) return VC_EINVAL;
-        if (a.op == Op::DebugKeysched && (!a.kIR[f] || !a.kD[f] || !a.kB[f])) return VC_EINVAL;
+        if ((a.op == Op::DebugKeysched || a.op == Op::DebugKeygen) && (!a.kIR[f] || !a.kD[f] || !a.kB[f]))
+            return VC_EINVAL;
         if (uses_scratch && scratch_need(s, n, keysched_scratch, two_pass) > slot_bytes(ctx)) return VC_ENOMEM;
         if (uses_chain) {
             if (s.stream >= ctx->max_streams) return VC_EINVAL;
@@ -387,6 +384,7 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
     // ---- plan spans (consecutive frames whose scratch fits a slot) and parts ----
     const bool overlap = (encrypting || a.op == Op::Decrypt) && ctx->parts > 1;
     const size_t cap = slot_bytes(ctx);
+    uint8_t *const sbase = ctx->d_scratch;
     struct Part {
         size_t b, e;
         uint32_t span;
@@ -432,21 +430,22 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         ch.span = pt.span;
         ch.desc_begin = static_cast<uint32_t>(sp.first);
         ch.desc_end = static_cast<uint32_t>(sp.second);
-        // shape groups: stable order by (w, h, aligned)
+        // shape groups: stable order by (w, h, alignment class)
         std::vector<size_t> idx;
         for (size_t f = sp.first; f < sp.second; ++f) idx.push_back(f);
-        auto aligned_of = [&](size_t f) {
+        // alignment class (launch_shift): 2 = rows and pointers 16-byte
+        // aligned, 1 = 4-byte aligned, 0 = neither
+        auto align_of = [&](size_t f) {
             const vc_shape &s = a.shapes[f];
-            if (s.w % 4) return false;
-            const uintptr_t pin = reinterpret_cast<uintptr_t>(a.in ? a.in[f] : nullptr);
-            const uintptr_t pout = reinterpret_cast<uintptr_t>(a.out ? a.out[f] : nullptr);
-            if ((pin | pout) & 3) return false;
-            if (a.op == Op::DebugConfuse && (reinterpret_cast<uintptr_t>(a.dbgB[f]) & 3)) return false;
-            return true;
+            uintptr_t p = reinterpret_cast<uintptr_t>(a.in ? a.in[f] : nullptr) |
+                          reinterpret_cast<uintptr_t>(a.out ? a.out[f] : nullptr);
+            if (a.op == Op::DebugConfuse) p |= reinterpret_cast<uintptr_t>(a.dbgB[f]);
+            if (s.w % 4 || (p & 3)) return 0;
+            return (s.w % 16 == 0 && (p & 15) == 0) ? 2 : 1;
         };
         std::stable_sort(idx.begin(), idx.end(), [&](size_t x, size_t y) {
             const vc_shape &p = a.shapes[x], &q = a.shapes[y];
-            return std::make_tuple(p.w, p.h, !aligned_of(x)) < std::make_tuple(q.w, q.h, !aligned_of(y));
+            return std::make_tuple(p.w, p.h, -align_of(x)) < std::make_tuple(q.w, q.h, -align_of(y));
         });
         for (size_t k = 0; k < idx.size(); ++k) {
             const size_t f = idx[k];
@@ -468,31 +467,32 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
             d.xstrip = 0;
             d.pad = 0;
             if (two_pass) {
-                d.X = ctx->d_scratch + off;
+                d.X = sbase + off;
                 off += align_up(d.L, 256);
                 // strip-major intermediate in the column pass's strips
-                d.xstrip = layout_strip(ctx, s.w, choose_tiling(ctx, dec_kernel, s.w, s.h).strip, aligned_of(f));
+                d.xstrip = shift_xstrip(s.w, choose_tiling(ctx, dec_kernel, s.w, s.h).strip, align_of(f),
+                                        ctx->lds_limit);
             }
             if (keysched_scratch) {
                 const uint64_t ND = 3ull * s.h + 3ull * s.w;
-                d.B = ctx->d_scratch + off;
+                d.B = sbase + off;
                 off += align_up(d.L, 256);
-                d.D = reinterpret_cast<uint16_t *>(ctx->d_scratch + off);
+                d.D = reinterpret_cast<uint16_t *>(sbase + off);
                 off += align_up(2 * ND, 256);
-                d.IR = reinterpret_cast<double *>(ctx->d_scratch + off);
+                d.IR = reinterpret_cast<double *>(sbase + off);
                 off += align_up(64ull * n, 256);
             } else if (a.op == Op::DebugConfuse) {
                 d.D = const_cast<uint16_t *>(a.dbgD[f]);
                 d.B = const_cast<uint8_t *>(a.dbgB[f]);
-            } else if (a.op == Op::DebugKeysched) {
+            } else if (a.op == Op::DebugKeysched || a.op == Op::DebugKeygen) {
                 d.IR = a.kIR[f];
                 d.D = a.kD[f];
                 d.B = a.kB[f];
             }
-            const bool al = aligned_of(f);
+            const int al = align_of(f);
             if (!ch.groups.empty()) {
                 Group &g = ch.groups.back();
-                if (g.w == s.w && g.h == s.h && g.aligned == al) {
+                if (g.w == s.w && g.h == s.h && g.align == al) {
                     g.count++;
                     continue;
                 }
@@ -553,12 +553,12 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         tun = choose_tiling(ctx, dec_kernel, g.w, g.h);
         if (!two_pass)
             return timed(ctx, dec_kernel ? K_DEC : K_ENC, ws, [&] {
-                return launch_confuse(dec_kernel, d_desc, g.first, g.count, g.w, g.h, g.aligned, tun, ws);
+                return launch_confuse(dec_kernel, d_desc, g.first, g.count, g.w, g.h, g.align >= 1, tun, ws);
             });
         for (int pass = 0; pass < 2; ++pass) {
             const int kid = dec_kernel ? (pass == 0 ? K_COL_DEC : K_ROW_DEC) : (pass == 0 ? K_ROW_ENC : K_COL_ENC);
             const hipError_t pe = timed(ctx, kid, ws, [&] {
-                return launch_shift(dec_kernel, pass, d_desc, g.first, g.count, g.w, g.h, g.aligned, tun,
+                return launch_shift(dec_kernel, pass, d_desc, g.first, g.count, g.w, g.h, g.align, tun,
                                     ctx->lds_limit, ws);
             });
             if (pe != hipSuccess) return pe;
@@ -569,6 +569,12 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
     // ---- launches ----
     if (a.op == Op::Encrypt || a.op == Op::Hash) {
         e = timed(ctx, K_SHA, s, [&] { return launch_sha256_subframes(d_desc, static_cast<uint32_t>(count), n, s); });
+        if (e != hipSuccess) return map_err(e);
+    }
+    if (a.op == Op::DebugKeygen) {
+        e = timed(ctx, K_KEYGEN, s, [&] {
+            return launch_lhcs_keygen(d_desc, static_cast<uint32_t>(count), n, ctx->key.gamma, ctx->d_flags, s);
+        });
         if (e != hipSuccess) return map_err(e);
     }
     if (uses_chain) {
@@ -920,6 +926,20 @@ int vc_debug_confuse(vc_cipher *ctx, int decrypt, size_t count, const uint8_t *c
     return locked_call(ctx, a);
 }
 
+int vc_debug_keygen(vc_cipher *ctx, size_t count, const vc_shape *shapes, const double *const *IR,
+                    uint16_t *const *D, uint8_t *const *B, void *stream) {
+    if (count && (!shapes || !IR || !D || !B)) return VC_EINVAL;
+    CallArgs a{};
+    a.op = Op::DebugKeygen;
+    a.count = count;
+    a.shapes = shapes;
+    a.kIR = const_cast<double *const *>(IR);
+    a.kD = D;
+    a.kB = B;
+    a.stream = static_cast<hipStream_t>(stream);
+    return locked_call(ctx, a);
+}
+
 int vc_debug_keysched(vc_cipher *ctx, size_t count, const vc_shape *shapes, const uint8_t *hashes,
                       double *const *IR, uint16_t *const *D, uint8_t *const *B, void *stream) {
     if (count && (!shapes || !hashes || !IR || !D || !B)) return VC_EINVAL;
@@ -1082,11 +1102,16 @@ int vc_autotune(vc_cipher *ctx, int decrypt, uint32_t w, uint32_t h, uint32_t fr
         if (e == hipSuccess)
             e = hipMemcpyAsync(d_desc, desc.data(), sizeof(FrameDesc) * frames, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
-        const bool aligned = (w % 4) == 0;
-        const uint32_t wcap = std::max<uint32_t>(4, (w + 3) / 4 * 4);
+        // buffers are 256-byte aligned: the alignment class is the rows'
+        const int align = (w % 16 == 0) ? 2 : (w % 4 == 0) ? 1 : 0;
+        // candidate strips: bytes of a row (two-pass) or pixels (single pass)
+        const uint32_t cap = ctx->passes == 2
+                                 ? std::max<uint32_t>(4, 1u << (32 - __builtin_clz(std::max<uint32_t>(3 * w, 2) - 1)))
+                                 : std::max<uint32_t>(4, (w + 3) / 4 * 4);
+        const uint32_t widest = ctx->passes == 2 ? 128 : 64;
         float best = 1e30f;
-        for (uint32_t wt = 4; wt <= 64 && e == hipSuccess; wt *= 2) {
-            if (wt > wcap) break;
+        for (uint32_t wt = 4; wt <= widest && e == hipSuccess; wt *= 2) {
+            if (wt > cap) break;
             const uint32_t lds = ctx->passes == 2 ? shift_col_lds_bytes(h, wt) : confuse_lds_bytes(decrypt, h, wt);
             if (lds > ctx->lds_limit) continue;
             for (uint32_t nt : {256u, 512u, 1024u}) {
@@ -1097,7 +1122,7 @@ int vc_autotune(vc_cipher *ctx, int decrypt, uint32_t w, uint32_t h, uint32_t fr
                 // the strip-tiled pass only (the row pass does not depend on the
                 // tiling), on the layout that the strip implies
                 if (ctx->passes == 2) {
-                    const uint32_t ls = layout_strip(ctx, w, wt, aligned);
+                    const uint32_t ls = shift_xstrip(w, wt, align, ctx->lds_limit);
                     if (desc[0].xstrip != ls) {
                         for (auto &dd : desc) dd.xstrip = ls;
                         e = hipMemcpyAsync(d_desc, desc.data(), sizeof(FrameDesc) * frames, hipMemcpyHostToDevice,
@@ -1108,9 +1133,9 @@ int vc_autotune(vc_cipher *ctx, int decrypt, uint32_t w, uint32_t h, uint32_t fr
                 }
                 auto run = [&] {
                     if (ctx->passes == 2)
-                        return launch_shift(decrypt, decrypt ? 0 : 1, d_desc, 0, frames, w, h, aligned, t,
+                        return launch_shift(decrypt, decrypt ? 0 : 1, d_desc, 0, frames, w, h, align, t,
                                             ctx->lds_limit, st);
-                    return launch_confuse(decrypt, d_desc, 0, frames, w, h, aligned, t, st);
+                    return launch_confuse(decrypt, d_desc, 0, frames, w, h, align >= 1, t, st);
                 };
                 e = run();  // warm-up
                 if (e == hipSuccess) e = hipEventRecord(e0, st);
@@ -1305,8 +1330,7 @@ size_t vc_scratch_per_frame(uint32_t w, uint32_t h, uint32_t n) {
 
 int vc_set_tuning(vc_cipher *ctx, uint32_t strip_width, uint32_t threads, int xcd_map) {
     if (!ctx) return VC_EINVAL;
-    if (strip_width && (strip_width % 4 || strip_width < 4 || strip_width > 64 ||
-                        (strip_width & (strip_width - 1))))
+    if (strip_width && (strip_width < 4 || strip_width > 128 || (strip_width & (strip_width - 1))))
         return VC_EINVAL;
     if (threads && threads != 256 && threads != 512 && threads != 1024) return VC_EINVAL;
     std::lock_guard<std::mutex> lk(ctx->mu);

@@ -34,16 +34,6 @@ namespace {
 
 typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
 
-// x mod m for x < 2^16 and 1 <= m < 2^21: float reciprocal estimate of the
-// quotient (off by at most one) plus one correction.
-__device__ __forceinline__ uint32_t mod16(uint32_t x, uint32_t m, float inv_m) {
-    const uint32_t q = static_cast<uint32_t>(static_cast<float>(x) * inv_m);
-    int32_t r = static_cast<int32_t>(x) - static_cast<int32_t>(q * m);
-    if (r < 0) r += static_cast<int32_t>(m);
-    if (r >= static_cast<int32_t>(m)) r -= static_cast<int32_t>(m);
-    return static_cast<uint32_t>(r);
-}
-
 // Workgroup -> (frame within the launch, strip).  With xcd_map the
 // hardware's round-robin placement of consecutive workgroups over the 8 XCDs
 // is undone: XCD x (workgroups g with g % 8 == x) gets frames x, x+8, ...,
@@ -162,10 +152,10 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(5, 8))) void
     }
 
     // Phase 0: distances, reduced once.
-    for (uint32_t it = threadIdx.x; it < 3 * h; it += NT) dhS[it] = mod16(D[it], W8, geo.inv_W8);
+    for (uint32_t it = threadIdx.x; it < 3 * h; it += NT) dhS[it] = mod_u16(D[it], geo.mod_W8);
     for (uint32_t it = threadIdx.x; it < 3 * wt; it += NT) {
         const uint32_t c = it / wt, k = it - c * wt;
-        dvS[c * WT + k] = mod16(D[3 * h + c * w + j0 + k], h, geo.inv_h);
+        dvS[c * WT + k] = mod_u16(D[3 * h + c * w + j0 + k], geo.mod_h);
     }
     __syncthreads();
 
@@ -324,11 +314,11 @@ __global__ __launch_bounds__(NT) void confuse_xor_dec(const FrameDesc *__restric
 
     // Phase 0: distances (column distances for k = 0..wt, the last being
     // column je).
-    for (uint32_t it = threadIdx.x; it < 3 * h; it += NT) dhS[it] = mod16(D[it], W8, geo.inv_W8);
+    for (uint32_t it = threadIdx.x; it < 3 * h; it += NT) dhS[it] = mod_u16(D[it], geo.mod_W8);
     for (uint32_t it = threadIdx.x; it < 3 * (wt + 1); it += NT) {
         const uint32_t c = it / (wt + 1), k = it - c * (wt + 1);
         const uint32_t j = (k < wt) ? j0 + k : je;
-        dvS[c * CS + k] = mod16(D[3 * h + c * w + j], h, geo.inv_h);
+        dvS[c * CS + k] = mod_u16(D[3 * h + c * w + j], geo.mod_h);
     }
     __syncthreads();
 
@@ -493,8 +483,8 @@ hipError_t launch_confuse(int decrypt, const FrameDesc *d_desc, uint32_t first, 
     g.h = h;
     g.W8 = 8 * w;
     g.row_bytes = 3 * w;
-    g.inv_h = 1.0f / static_cast<float>(h);
-    g.inv_W8 = 1.0f / static_cast<float>(g.W8);
+    g.mod_h = mod_magic(h);
+    g.mod_W8 = mod_magic(g.W8);
     switch (t.strip) {
     case 4: return launch_wt<4>(decrypt, d_desc, first, count, g, aligned, t, s);
     case 8: return launch_wt<8>(decrypt, d_desc, first, count, g, aligned, t, s);

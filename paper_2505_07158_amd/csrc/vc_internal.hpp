@@ -29,11 +29,12 @@ struct FrameDesc {
     uint32_t w, h;
     uint64_t L;          // 3wh
     // Layout of X: 0 = row-major (the frame's own layout), else strip-major
-    // with strips of that many pixels (WT, a power of two that divides w;
-    // the column pass's strip width): byte c of row r lies in strip
-    // s = c / 3WT at s*h*3WT + r*3WT + c % 3WT, so that a strip's rows are
-    // contiguous and the column pass reads (encrypt) or writes (decrypt)
-    // them linearly.
+    // with strips of SB = xstrip bytes of each row (the column pass's strip
+    // width, a power of two >= 16; rows of 3w bytes, a multiple of 16): byte
+    // k of row r lies in strip s = k / SB, at s*SB*h + r*sb + k % SB, where
+    // sb = min(SB, 3w - s*SB) is the strip's width (only the last strip can
+    // be narrower), so that a strip's rows are contiguous and the column
+    // pass reads (encrypt) or writes (decrypt) them linearly.
     uint32_t xstrip;
     uint32_t pad;
 };
@@ -66,14 +67,33 @@ enum KernelId {
     K_COUNT = 9
 };
 
+// x mod m for a 16-bit x and 1 <= m < 2^20, by multiplication only:
+// with M = ceil(2^48 / m) and e = M*m - 2^48 (0 <= e < m),
+// x*M / 2^48 = x/m + x*e / (m * 2^48), and x*e < 2^36, so the second term
+// stays below 1/m and floor(x*M / 2^48) is the exact quotient.  x*M fits
+// in 64 bits (M <= 2^48).
+struct ModMagic {
+    uint32_t m, pad;
+    uint64_t M;
+};
+__host__ __device__ inline ModMagic mod_magic(uint32_t m) {
+    return ModMagic{m, 0, ((uint64_t(1) << 48) + m - 1) / m};
+}
+__device__ __forceinline__ uint32_t mod_u16(uint32_t x, const ModMagic &g) {
+    const uint32_t q = static_cast<uint32_t>((static_cast<uint64_t>(x) * g.M) >> 48);
+    return x - q * g.m;
+}
+
 // Frame geometry of a confusion launch (all frames of a launch share it).
 struct Geometry {
     uint32_t w, h, W8, row_bytes;  // W8 = 8w bits per channel row, row_bytes = 3w
-    float inv_h, inv_W8;           // reciprocals for the distance reductions
+    ModMagic mod_h, mod_W8;        // for the distance reductions d mod h, d mod 8w
 };
 
 struct ConfuseTuning {
-    uint32_t strip;      // pixels per strip (multiple of 4)
+    // two-pass form: bytes of a row per column-pass strip (4..128, a power
+    // of two); single-pass form: pixels per strip (4..64)
+    uint32_t strip;
     uint32_t threads;    // 256, 512 or 1024
     int xcd_map;         // keep all strips of a frame on one XCD
 };
@@ -105,13 +125,24 @@ uint32_t confuse_lds_bytes(int decrypt, uint32_t h, uint32_t strip);
 hipError_t confuse_configure(uint32_t lds_limit);
 // Two-pass confusion (vc_shift.hip).  pass 0 then pass 1: encrypt = rows,
 // then columns + XOR; decrypt = XOR + columns, then rows.  Reads and writes
-// FrameDesc::X as the intermediate.
+// FrameDesc::X as the intermediate.  `align` is what every frame of the
+// launch satisfies: 0 nothing, 1 rows and frame pointers 4-byte aligned
+// (w % 4 == 0), 2 rows and pointers (frames, output, keystream) 16-byte
+// aligned (w % 16 == 0); the 16-byte column kernels run only for align 2
+// with a strip-major X of the launch's strip width.
 hipError_t launch_shift(int decrypt, int pass, const FrameDesc *d_desc, uint32_t first, uint32_t count, uint32_t w,
-                        uint32_t h, bool aligned, const ConfuseTuning &t, uint32_t lds_limit, hipStream_t s);
+                        uint32_t h, int align, const ConfuseTuning &t, uint32_t lds_limit, hipStream_t s);
+// Widest column-pass strip (bytes) whose full-height staging fits lds_bytes
+// for height h, 0 if none.
 uint32_t shift_max_strip(uint32_t h, uint32_t lds_bytes);
 // True when the row pass stages its rows in LDS for frames of width w (the
 // only form that reads or writes the strip-major intermediate image).
 bool shift_rows_staged(uint32_t w, uint32_t lds_bytes);
+// Layout of the intermediate image for frames of width w whose column pass
+// uses strips of `strip` bytes under alignment class `align`: the strip
+// width when X is strip-major (FrameDesc::xstrip), else 0 (row-major).
+// launch_shift picks its column kernel by the same rule.
+uint32_t shift_xstrip(uint32_t w, uint32_t strip, int align, uint32_t lds_limit);
 uint32_t shift_col_lds_bytes(uint32_t h, uint32_t strip);
 hipError_t shift_configure(uint32_t lds_limit);
 // Statistics (vc_stats.hip).  hist: count x 3 x 256 (frame) or count x

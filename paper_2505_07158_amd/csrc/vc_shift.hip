@@ -21,22 +21,29 @@
 // channel (encrypt) or scatter bytes of three channels to random places of
 // every output row (decrypt, partial-line writes).  Two passes move 15 B/px
 // instead of the 9 B/px minimum but never fetch or write a partial line.
+//
+// The column rotation moves each byte column k = 3j + c of the 3w-byte rows
+// on its own (by d_v(c, j)); it does not care where pixels begin.  So the
+// column pass cuts the rows into strips of SB bytes (a power of two, up to
+// 128 = one cache line), not of whole pixels: with rows of a multiple of 16
+// bytes, every row segment of the frame, of B and of the output is then
+// whole 16-byte words, and at SB = 128 (1080p: a full-height strip is
+// 1080 x 128 bytes of LDS) every HBM access of both passes covers whole
+// 128-byte lines.  The intermediate image is stored strip-major in those
+// strips (FrameDesc::xstrip), so the column pass stages (encrypt) or writes
+// (decrypt) a strip as one contiguous block.
 #include "vc_internal.hpp"
 
 namespace vc {
 namespace {
 
-__device__ __forceinline__ uint32_t mod16(uint32_t x, uint32_t m, float inv_m) {
-    const uint32_t q = static_cast<uint32_t>(static_cast<float>(x) * inv_m);
-    int32_t r = static_cast<int32_t>(x) - static_cast<int32_t>(q * m);
-    if (r < 0) r += static_cast<int32_t>(m);
-    if (r >= static_cast<int32_t>(m)) r -= static_cast<int32_t>(m);
-    return static_cast<uint32_t>(r);
-}
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+__host__ __device__ constexpr uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 
 // Workgroup -> (frame within the launch, strip), all strips of a frame on
 // one XCD (the hardware places consecutive workgroups round-robin on the 8
-// XCDs), so that neighbouring strips' partial cache lines meet in one L2.
+// XCDs), so that neighbouring strips' accesses meet in one L2.
 __device__ __forceinline__ void map_strip(uint32_t g, uint32_t nstrips, int xcd_map, uint32_t &fl, uint32_t &strip) {
     if (xcd_map) {
         const uint32_t x = g & 7, l = g >> 3;
@@ -52,8 +59,6 @@ __device__ __forceinline__ void map_strip(uint32_t g, uint32_t nstrips, int xcd_
 // ----------------------------------------------------------------------
 // Row pass
 // ----------------------------------------------------------------------
-typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-
 constexpr uint32_t kRowThreads = 256;
 constexpr uint32_t kRowsPerGroup = 4;
 constexpr uint32_t kRowShiftTable = 16 * kRowsPerGroup;  // LDS bytes of the rows' shift amounts
@@ -81,10 +86,10 @@ __device__ __forceinline__ uint32_t shifted4(Ptr row, uint32_t s, uint32_t w) {
 }
 
 // Pixels 4m..4m+3 of all three channels of one row: twelve bytes (pixel k,
-// channel c at byte 3k + c), stored as three dwords when aligned.
+// channel c at byte 3k + c), as three dwords.
 template <typename Ptr>
-__device__ __forceinline__ void shift_group(Ptr row, VC_GLOBAL uint8_t *piece, const uint32_t sh[3], uint32_t m,
-                                            uint32_t w, uint32_t W8, int aligned) {
+__device__ __forceinline__ void shift12(Ptr row, const uint32_t sh[3], uint32_t m, uint32_t w, uint32_t W8,
+                                        uint32_t dw[3]) {
     uint32_t o[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
@@ -92,16 +97,21 @@ __device__ __forceinline__ void shift_group(Ptr row, VC_GLOBAL uint8_t *piece, c
         if (s >= W8) s -= W8;
         o[c] = shifted4(row + c, s, w);
     }
-    const uint32_t d0 = (o[0] & 0xFFu) | ((o[1] & 0xFFu) << 8) | ((o[2] & 0xFFu) << 16) | (o[0] << 16 & 0xFF000000u);
-    const uint32_t d1 = ((o[1] >> 8) & 0xFFu) | (o[2] & 0xFF00u) | (o[0] & 0xFF0000u) | ((o[1] << 8) & 0xFF000000u);
-    const uint32_t d2 = ((o[2] >> 16) & 0xFFu) | ((o[0] >> 16) & 0xFF00u) | ((o[1] >> 8) & 0xFF0000u) | (o[2] & 0xFF000000u);
+    dw[0] = (o[0] & 0xFFu) | ((o[1] & 0xFFu) << 8) | ((o[2] & 0xFFu) << 16) | (o[0] << 16 & 0xFF000000u);
+    dw[1] = ((o[1] >> 8) & 0xFFu) | (o[2] & 0xFF00u) | (o[0] & 0xFF0000u) | ((o[1] << 8) & 0xFF000000u);
+    dw[2] = ((o[2] >> 16) & 0xFFu) | ((o[0] >> 16) & 0xFF00u) | ((o[1] >> 8) & 0xFF0000u) | (o[2] & 0xFF000000u);
+}
+
+// Stores the twelve bytes of pixels 4m..4m+3 at `piece` (row-major):
+// three dwords when aligned, else the bytes that lie inside the row.
+__device__ __forceinline__ void store12(VC_GLOBAL uint8_t *piece, const uint32_t dw[3], uint32_t m, uint32_t w,
+                                        int aligned) {
     if (aligned && 4 * m + 4 <= w) {
         VC_GLOBAL uint32_t *q4 = reinterpret_cast<VC_GLOBAL uint32_t *>(piece);
-        q4[0] = d0;
-        q4[1] = d1;
-        q4[2] = d2;
+        q4[0] = dw[0];
+        q4[1] = dw[1];
+        q4[2] = dw[2];
     } else {
-        const uint32_t dw[3] = {d0, d1, d2};
         const uint32_t nb = 3 * ((w - 4 * m < 4) ? w - 4 * m : 4);
         for (uint32_t b = 0; b < nb; ++b) piece[b] = static_cast<uint8_t>(dw[b >> 2] >> (8 * (b & 3)));
     }
@@ -111,7 +121,7 @@ __device__ __forceinline__ void row_shifts(const VC_GLOBAL uint16_t *D, uint32_t
                                            bool inv, uint32_t sh[3]) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const uint32_t dh = mod16(D[c * h + r], geo.W8, geo.inv_W8);
+        const uint32_t dh = mod_u16(D[c * h + r], geo.mod_W8);
         sh[c] = inv ? dh : (dh ? geo.W8 - dh : 0);
     }
 }
@@ -123,7 +133,8 @@ __device__ __forceinline__ void row_shifts(const VC_GLOBAL uint16_t *D, uint32_t
 // workgroup are first copied to LDS at once (16-byte loads when rows and
 // pointers allow, so that many bytes are in flight), then shifted from
 // there; otherwise (rows too long for LDS) bytes are read from global
-// memory row by row.
+// memory row by row.  The intermediate X is row-major or strip-major
+// (FrameDesc::xstrip; only with STAGE and 16-byte rows).
 template <bool INV, bool STAGE>
 __global__ __launch_bounds__(kRowThreads) void row_shift(const FrameDesc *__restrict__ desc, uint32_t first,
                                                        uint32_t nframes, Geometry geo, uint32_t groups_per_frame,
@@ -143,32 +154,23 @@ __global__ __launch_bounds__(kRowThreads) void row_shift(const FrameDesc *__rest
         // the rows' shift amounts sit after the rows
         uint32_t(*shS)[3] = reinterpret_cast<uint32_t(*)[3]>(rowbuf + kRowsPerGroup * lds_row);
         if (threadIdx.x < nr) row_shifts(D, r0 + threadIdx.x, h, geo, INV, shS[threadIdx.x]);
-        // strip-major X (the host sets it only for aligned rows whose width
-        // is a multiple of the strip): decryption reads T from the strips'
-        // runs of nr rows, encryption writes S to them
-        const uint32_t xs = d.xstrip, RSx = 3 * xs;
+        const uint32_t xs = d.xstrip;
         const bool x_sm = xs != 0;
+        const uint32_t sl = x_sm ? static_cast<uint32_t>(__builtin_ctz(xs)) : 0;
         if (INV && x_sm) {
-            const uint32_t nstr = w / xs;
-            const uint64_t run0 = static_cast<uint64_t>(r0) * RSx;
-            if (RSx % 16 == 0) {
-                const uint32_t per = RSx / 16, per_strip = nr * per, n16 = nstr * per_strip;
-                for (uint32_t k = threadIdx.x; k < n16; k += kRowThreads) {
-                    const uint32_t st = k / per_strip, within = k - st * per_strip;
-                    const uint32_t rr = within / per, e = within - rr * per;
-                    const uint64_t goff = static_cast<uint64_t>(st) * h * RSx + run0 + static_cast<uint64_t>(within) * 16;
-                    *reinterpret_cast<u32x4 *>(rowbuf + rr * lds_row + st * RSx + 16 * e) =
-                        *reinterpret_cast<const VC_GLOBAL u32x4 *>(src + goff);
-                }
-            } else {
-                const uint32_t per = RSx / 4, per_strip = nr * per, n4 = nstr * per_strip;
-                for (uint32_t k = threadIdx.x; k < n4; k += kRowThreads) {
-                    const uint32_t st = k / per_strip, within = k - st * per_strip;
-                    const uint32_t rr = within / per, e = within - rr * per;
-                    const uint64_t goff = static_cast<uint64_t>(st) * h * RSx + run0 + static_cast<uint64_t>(within) * 4;
-                    *reinterpret_cast<uint32_t *>(rowbuf + rr * lds_row + st * RSx + 4 * e) =
-                        *reinterpret_cast<const VC_GLOBAL uint32_t *>(src + goff);
-                }
+            // T is strip-major: rows r0 .. r0+nr-1 of a strip are one
+            // contiguous run of 16-byte words, read in memory order (every
+            // strip but the last has nr * SB / 16 of them)
+            const uint32_t ns = (rb + xs - 1) >> sl, cps = nr * (xs / 16), n16 = nr * (rb / 16);
+            for (uint32_t k = threadIdx.x; k < n16; k += kRowThreads) {
+                uint32_t st = k / cps;
+                if (st > ns - 1) st = ns - 1;
+                const uint32_t k0 = st << sl, sbw = (rb - k0 < xs) ? rb - k0 : xs;
+                const uint32_t within = k - st * cps, q16 = sbw / 16;
+                const uint32_t rr = within / q16, e = within - rr * q16;
+                *reinterpret_cast<u32x4 *>(rowbuf + rr * lds_row + k0 + 16 * e) =
+                    *reinterpret_cast<const VC_GLOBAL u32x4 *>(src + static_cast<uint64_t>(k0) * h +
+                                                               static_cast<uint64_t>(r0) * sbw + 16 * within);
             }
         } else {
             const VC_GLOBAL uint8_t *s0 = src + static_cast<uint64_t>(r0) * rb;
@@ -198,23 +200,43 @@ __global__ __launch_bounds__(kRowThreads) void row_shift(const FrameDesc *__rest
         }
         __syncthreads();
         if (!INV && x_sm) {
-            // lanes in output order: strip, row, 12-byte piece, so that a wave
-            // writes whole runs of nr rows of consecutive strips
-            const uint32_t pps = xs / 4, per_strip = nr * pps, nt = (w / xs) * per_strip;
-            for (uint32_t t = threadIdx.x; t < nt; t += kRowThreads) {
+            // S is strip-major (w % 16 == 0, so every 12-byte piece lies in
+            // the row).  Lanes are ordered strip, row, piece, so that a wave
+            // writes rows r0 .. r0+nr-1 of a strip -- one contiguous run of
+            // whole lines -- together; a piece that straddles two strips is
+            // made by a lane of each, and each stores its own strip's dwords.
+            const uint32_t slots = (xs + 11) / 12 + 1;  // pieces that can touch one strip row
+            const uint32_t per_strip = nr * slots, total = ((rb + xs - 1) >> sl) * per_strip;
+            for (uint32_t t = threadIdx.x; t < total; t += kRowThreads) {
                 const uint32_t st = t / per_strip, within = t - st * per_strip;
-                const uint32_t rr = within / pps, kk = within - rr * pps;
+                const uint32_t rr = within / slots, slot = within - rr * slots;
+                const uint32_t k0 = st << sl, sbw = (rb - k0 < xs) ? rb - k0 : xs;
+                const uint32_t m = k0 / 12 + slot;
+                if (12 * m >= k0 + sbw) continue;  // past the strip's last piece
                 const uint32_t sh[3] = {shS[rr][0], shS[rr][1], shS[rr][2]};
-                VC_GLOBAL uint8_t *piece = dst + static_cast<uint64_t>(st) * h * RSx +
-                                           static_cast<uint64_t>(r0 + rr) * RSx + 12 * kk;
-                shift_group(rowbuf + rr * lds_row, piece, sh, st * pps + kk, w, W8, aligned);
+                uint32_t dw[3];
+                shift12(rowbuf + rr * lds_row, sh, m, w, W8, dw);
+                VC_GLOBAL uint8_t *run = dst + static_cast<uint64_t>(k0) * h + static_cast<uint64_t>(r0 + rr) * sbw;
+                if (12 * m >= k0 && 12 * m + 12 <= k0 + sbw) {
+                    VC_GLOBAL uint32_t *q4 = reinterpret_cast<VC_GLOBAL uint32_t *>(run + (12 * m - k0));
+                    q4[0] = dw[0];
+                    q4[1] = dw[1];
+                    q4[2] = dw[2];
+                } else {
+#pragma unroll
+                    for (uint32_t e = 0; e < 3; ++e) {
+                        const uint32_t k = 12 * m + 4 * e;
+                        if (k >= k0 && k < k0 + sbw) *reinterpret_cast<VC_GLOBAL uint32_t *>(run + (k - k0)) = dw[e];
+                    }
+                }
             }
         } else {
             for (uint32_t k = threadIdx.x; k < nr * ngroups; k += kRowThreads) {
                 const uint32_t rr = k / ngroups, m = k - rr * ngroups;
                 const uint32_t sh[3] = {shS[rr][0], shS[rr][1], shS[rr][2]};
-                shift_group(rowbuf + rr * lds_row, dst + static_cast<uint64_t>(r0 + rr) * rb + 12 * m, sh, m, w, W8,
-                            aligned);
+                uint32_t dw[3];
+                shift12(rowbuf + rr * lds_row, sh, m, w, W8, dw);
+                store12(dst + static_cast<uint64_t>(r0 + rr) * rb + 12 * m, dw, m, w, aligned);
             }
         }
     } else {
@@ -224,8 +246,11 @@ __global__ __launch_bounds__(kRowThreads) void row_shift(const FrameDesc *__rest
             row_shifts(D, r, h, geo, INV, sh);
             const VC_GLOBAL uint8_t *srow = src + static_cast<uint64_t>(r) * rb;
             VC_GLOBAL uint8_t *drow = dst + static_cast<uint64_t>(r) * rb;
-            for (uint32_t m = threadIdx.x; m < ngroups; m += kRowThreads)
-                shift_group(srow, drow + 12 * m, sh, m, w, W8, aligned);
+            for (uint32_t m = threadIdx.x; m < ngroups; m += kRowThreads) {
+                uint32_t dw[3];
+                shift12(srow, sh, m, w, W8, dw);
+                store12(drow + 12 * m, dw, m, w, aligned);
+            }
         }
     }
 }
@@ -233,195 +258,240 @@ __global__ __launch_bounds__(kRowThreads) void row_shift(const FrameDesc *__rest
 // ----------------------------------------------------------------------
 // Column pass
 // ----------------------------------------------------------------------
-// LDS: the strip (h rows of 3*WT bytes), then the strip's column distances
-// d_v mod h (3 x WT words).
-template <int WT>
-struct ColLayout {
-    static constexpr uint32_t RS = 3 * WT;
-    __host__ __device__ static uint32_t dv_off(uint32_t h) { return (h * RS + 15u) & ~15u; }
-    __host__ __device__ static uint32_t bytes(uint32_t h) { return dv_off(h) + 4 * 3 * WT; }
-};
+// LDS: the strip (h rows of at most SB bytes), then the strip's column
+// distances (SB words: the source-row offset of each byte column).
+__host__ __device__ inline uint32_t col_dv_off(uint32_t h, uint32_t SB) { return align16(h * SB); }
+__host__ __device__ inline uint32_t col_lds_bytes(uint32_t h, uint32_t SB) { return col_dv_off(h, SB) + 4 * SB; }
 
-// One workgroup owns a full-height strip of WT pixel columns (all three
-// channels) of one frame.  Forward: stage S, then C[i] = S[(i - d_v) mod h]
-// ^ B[i].  Inverse: stage C ^ B, then T[r] = (C ^ B)[(r + d_v) mod h].
-// Aligned path: dword loads and stores (w % 4 == 0, 4-byte aligned frames);
-// otherwise bytes.
-template <int WT, int NT, bool INV>
-__global__ __launch_bounds__(NT) void col_shift(const FrameDesc *__restrict__ desc, uint32_t first, uint32_t nframes,
-                                                Geometry geo, uint32_t nstrips, int xcd_map, int aligned) {
+// Byte columns k0 .. k0 + sb - 1 of the strip: dvS[kk] = d_v mod h of the
+// column (forward: the output row i takes source row (i - dvS) mod h) or
+// h - d_v mod h (inverse: row r of T takes row (r + d_v) mod h of C ^ B);
+// both read (i + h - dvS) mod h.
+__device__ __forceinline__ void col_distances(const VC_GLOBAL uint16_t *D, const Geometry &geo, uint32_t k0,
+                                              uint32_t sb, bool inv, uint32_t *dvS, uint32_t nt) {
+    const uint32_t h = geo.h, w = geo.w;
+    for (uint32_t kk = threadIdx.x; kk < sb; kk += nt) {
+        const uint32_t k = k0 + kk, j = k / 3, c = k - 3 * j;
+        const uint32_t dv = mod_u16(D[3 * h + c * w + j], geo.mod_h);
+        dvS[kk] = inv ? (dv ? h - dv : 0) : dv;
+    }
+}
+
+// 16-byte column pass: rows of a multiple of 16 bytes, frames, outputs and
+// keystream 16-byte aligned, X strip-major with strips of SB bytes.  One
+// workgroup owns a full-height strip of one frame; thread t handles the
+// 16-byte word q = t % nq of rows i0, i0 + RP, ... (i0 = t / nq).
+//   forward: stage the strip of S (one contiguous block of X) with
+//            B's first rows already in flight, then
+//            C[i][word] = gather of S rows (i - d_v) mod h ^ B[i][word];
+//   inverse: stage C ^ B (16-byte words of every row), then
+//            T[r][word] = gather of rows (r + d_v) mod h, stored to the
+//            strip's contiguous block of X.
+template <int SB, int NT, bool INV>
+__global__ __launch_bounds__(NT) void col_shift_v(const FrameDesc *__restrict__ desc, uint32_t first, uint32_t nframes,
+                                                  Geometry geo, uint32_t nstrips, int xcd_map) {
     extern __shared__ __align__(16) uint8_t smem[];
-    using Lay = ColLayout<WT>;
-    constexpr uint32_t RS = Lay::RS;
-    constexpr uint32_t GPR = 3 * WT / 4;  // dwords per full strip row
-    constexpr uint32_t RP = NT / GPR;     // rows per pass
-    constexpr uint32_t kUnroll = 8;       // staging passes in flight per thread
-
+    constexpr uint32_t U = NT >= 1024 ? 2 : 4;  // rows in flight per thread (1024 threads: within 56 VGPRs)
     uint32_t fl, strip;
     map_strip(blockIdx.x, nstrips, xcd_map, fl, strip);
     if (fl >= nframes) return;
     const FrameDesc d = desc[first + fl];
-    const uint32_t w = geo.w, h = geo.h, rb = geo.row_bytes;
-    const uint32_t j0 = strip * WT;
-    const uint32_t wt = (w - j0 < static_cast<uint32_t>(WT)) ? w - j0 : WT;
-    // Each operand is addressed as base + row * stride: row-major (the
-    // strip's columns of each frame row) or, for the intermediate image X,
-    // strip-major (the strip's rows contiguous, stride 3*WT; the host sets
-    // that layout only when its strip width is this kernel's WT and the rows
-    // are aligned).
-    const bool x_sm = d.xstrip != 0;
-    const uint64_t sm_base = static_cast<uint64_t>(strip) * h * RS;
-    const VC_GLOBAL uint8_t *__restrict__ in =
-        INV ? gmem(d.in) + 3 * j0 : gmem(d.X) + (x_sm ? sm_base : 3 * j0);
-    const uint32_t in_stride = (!INV && x_sm) ? RS : rb;
-    const VC_GLOBAL uint8_t *__restrict__ Bp = gmem(d.B) + 3 * j0;
-    const uint32_t b_stride = rb;
-    VC_GLOBAL uint8_t *__restrict__ out = INV ? gmem(d.X) + (x_sm ? sm_base : 3 * j0) : gmem(d.out) + 3 * j0;
-    const uint32_t out_stride = (INV && x_sm) ? RS : rb;
-    const VC_GLOBAL uint16_t *__restrict__ D = gmem(d.D);
+    const uint32_t h = geo.h, rb = geo.row_bytes;
+    const uint32_t k0 = strip * SB;
+    const uint32_t sb = (rb - k0 < static_cast<uint32_t>(SB)) ? rb - k0 : SB;  // a multiple of 16
+    const uint32_t nq = sb >> 4;
+    const uint32_t RP = NT / nq;  // rows per pass
+    const uint32_t q = threadIdx.x % nq, i0 = threadIdx.x / nq;
+    const uint32_t np = (i0 < RP && i0 < h) ? (h - i0 + RP - 1) / RP : 0;  // rows of this thread
     uint8_t *S = smem;
-    uint32_t *dvS = reinterpret_cast<uint32_t *>(smem + Lay::dv_off(h));
+    uint32_t *dvS = reinterpret_cast<uint32_t *>(smem + col_dv_off(h, SB));
+    VC_GLOBAL uint8_t *Xs = gmem(d.X) + static_cast<uint64_t>(k0) * h;  // the strip's block of X
+    const VC_GLOBAL uint8_t *Bq = gmem(d.B) + k0 + 16 * q;
+    col_distances(gmem(d.D), geo, k0, sb, INV, dvS, NT);
 
-    for (uint32_t it = threadIdx.x; it < 3 * wt; it += NT) {
-        const uint32_t c = it / wt, k = it - c * wt;
-        const uint32_t dv = mod16(D[3 * h + c * w + j0 + k], h, geo.inv_h);
-        dvS[c * WT + k] = INV ? (dv ? h - dv : 0) : dv;  // source row = (i + h - dvS) mod h, forward and inverse
-    }
-
-    const uint32_t g = threadIdx.x % GPR, i0 = threadIdx.x / GPR;
-    const bool lane_on = aligned && i0 < RP && g < 3 * wt / 4;
-    if (aligned) {
-        if (!INV && x_sm && (static_cast<uint64_t>(h) * RS) % 16 == 0) {
-            // the strip of S is h*RS contiguous bytes, 16-byte aligned: a
-            // linear copy into LDS by every thread
-            const uint32_t n16 = h * RS / 16;
-            const VC_GLOBAL u32x4 *in4 = reinterpret_cast<const VC_GLOBAL u32x4 *>(in);
-            u32x4 *S4 = reinterpret_cast<u32x4 *>(S);
-            for (uint32_t k0 = threadIdx.x; k0 < n16; k0 += 4 * NT) {
-                u32x4 v[4];
+    u32x4 b[U];
+    if (!INV) {
+        // B of the first U rows in flight while the strip is staged
 #pragma unroll
-                for (uint32_t u = 0; u < 4; ++u)
-                    if (k0 + u * NT < n16) v[u] = in4[k0 + u * NT];
+        for (uint32_t u = 0; u < U; ++u)
+            if (u < np) b[u] = *reinterpret_cast<const VC_GLOBAL u32x4 *>(Bq + static_cast<uint64_t>(i0 + u * RP) * rb);
+        const uint32_t n16 = h * nq;
+        const VC_GLOBAL u32x4 *X4 = reinterpret_cast<const VC_GLOBAL u32x4 *>(Xs);
+        u32x4 *S4 = reinterpret_cast<u32x4 *>(S);
+        for (uint32_t k = threadIdx.x; k < n16; k += 4 * NT) {
+            u32x4 v[4];
 #pragma unroll
-                for (uint32_t u = 0; u < 4; ++u)
-                    if (k0 + u * NT < n16) S4[k0 + u * NT] = v[u];
-            }
-        } else if (lane_on) {
-            // stage: S row i, dword g  <-  in[i][g] (^ B[i][g] when inverse)
-            for (uint32_t base = i0; base < h; base += kUnroll * RP) {
-                uint32_t v[kUnroll], b[kUnroll];
+            for (uint32_t u = 0; u < 4; ++u)
+                if (k + u * NT < n16) v[u] = X4[k + u * NT];
 #pragma unroll
-                for (uint32_t u = 0; u < kUnroll; ++u) {
-                    const uint32_t i = base + u * RP;
-                    if (i < h) {
-                        v[u] = *reinterpret_cast<const VC_GLOBAL uint32_t *>(in + static_cast<uint64_t>(i) * in_stride +
-                                                                              4 * g);
-                        if (INV)
-                            b[u] = *reinterpret_cast<const VC_GLOBAL uint32_t *>(
-                                Bp + static_cast<uint64_t>(i) * b_stride + 4 * g);
-                    }
-                }
-#pragma unroll
-                for (uint32_t u = 0; u < kUnroll; ++u) {
-                    const uint32_t i = base + u * RP;
-                    if (i < h) reinterpret_cast<uint32_t *>(S + i * RS)[g] = INV ? (v[u] ^ b[u]) : v[u];
-                }
-            }
-        }
-        __syncthreads();
-        if (lane_on) {
-            uint32_t addr[4];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const uint32_t p = 4 * g + m, k = p / 3, c = p - 3 * k;
-                const uint32_t dv = dvS[c * WT + k];
-                const uint32_t r = (i0 >= dv) ? i0 - dv : i0 + h - dv;
-                addr[m] = r * RS + p;  // the strip is staged in frame byte order
-            }
-            const uint32_t stepA = (RP % h) * RS, wrapA = h * RS;
-            const uint64_t bstep = static_cast<uint64_t>(RP) * b_stride, ostep = static_cast<uint64_t>(RP) * out_stride;
-            uint64_t boff = static_cast<uint64_t>(i0) * b_stride + 4 * g;
-            uint64_t ooff = static_cast<uint64_t>(i0) * out_stride + 4 * g;
-            for (uint32_t base = i0; base < h; base += kUnroll * RP) {
-                uint32_t b[kUnroll];
-                if (!INV) {
-#pragma unroll
-                    for (uint32_t u = 0; u < kUnroll; ++u)
-                        if (base + u * RP < h)
-                            b[u] = *reinterpret_cast<const VC_GLOBAL uint32_t *>(Bp + boff + u * bstep);
-                }
-#pragma unroll
-                for (uint32_t u = 0; u < kUnroll; ++u) {
-                    if (base + u * RP < h) {
-                        uint32_t v = static_cast<uint32_t>(S[addr[0]]) | (static_cast<uint32_t>(S[addr[1]]) << 8) |
-                                     (static_cast<uint32_t>(S[addr[2]]) << 16) |
-                                     (static_cast<uint32_t>(S[addr[3]]) << 24);
-                        if (!INV) v ^= b[u];
-                        *reinterpret_cast<VC_GLOBAL uint32_t *>(out + ooff + u * ostep) = v;
-#pragma unroll
-                        for (int m = 0; m < 4; ++m) {
-                            addr[m] += stepA;
-                            if (addr[m] >= wrapA) addr[m] -= wrapA;
-                        }
-                    }
-                }
-                boff += kUnroll * bstep;
-                ooff += kUnroll * ostep;
-            }
+            for (uint32_t u = 0; u < 4; ++u)
+                if (k + u * NT < n16) S4[k + u * NT] = v[u];
         }
     } else {
-        const uint32_t rowlen = 3 * wt;
-        for (uint32_t it = threadIdx.x; it < h * rowlen; it += NT) {
-            const uint32_t i = it / rowlen, p = it - i * rowlen;
-            const uint8_t v = in[static_cast<uint64_t>(i) * in_stride + p];
-            S[i * RS + p] = INV ? (v ^ Bp[static_cast<uint64_t>(i) * b_stride + p]) : v;
+        const VC_GLOBAL uint8_t *Cq = gmem(d.in) + k0 + 16 * q;
+        for (uint32_t p0 = 0; p0 < np; p0 += U) {
+            u32x4 c[U];
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u) {
+                if (p0 + u < np) {
+                    const uint64_t off = static_cast<uint64_t>(i0 + (p0 + u) * RP) * rb;
+                    c[u] = *reinterpret_cast<const VC_GLOBAL u32x4 *>(Cq + off);
+                    b[u] = *reinterpret_cast<const VC_GLOBAL u32x4 *>(Bq + off);
+                }
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < U; ++u)
+                if (p0 + u < np)
+                    *reinterpret_cast<u32x4 *>(S + (i0 + (p0 + u) * RP) * sb + 16 * q) = c[u] ^ b[u];
         }
-        __syncthreads();
-        for (uint32_t it = threadIdx.x; it < h * rowlen; it += NT) {
-            const uint32_t i = it / rowlen, p = it - i * rowlen;
-            const uint32_t k = p / 3, c = p - 3 * k;
-            const uint32_t dv = dvS[c * WT + k];
-            const uint32_t r = (i >= dv) ? i - dv : i + h - dv;
-            const uint8_t v = S[r * RS + p];
-            out[static_cast<uint64_t>(i) * out_stride + p] =
-                INV ? v : static_cast<uint8_t>(v ^ Bp[static_cast<uint64_t>(i) * b_stride + p]);
+    }
+    __syncthreads();
+    if (np == 0) return;
+
+    // LDS byte address of each of the thread's 16 byte columns in its
+    // current row, stepped by RP rows (mod h) per pass
+    uint32_t a[16];
+#pragma unroll
+    for (uint32_t m = 0; m < 16; ++m) {
+        const uint32_t kk = 16 * q + m, dv = dvS[kk];
+        const uint32_t r = (i0 >= dv) ? i0 - dv : i0 + h - dv;
+        a[m] = r * sb + kk;
+    }
+    const uint32_t stepA = (RP % h) * sb, wrapA = h * sb;
+    VC_GLOBAL uint8_t *Oq = INV ? Xs + 16 * q : gmem(d.out) + k0 + 16 * q;
+    const uint32_t ostride = INV ? sb : rb;
+    for (uint32_t p0 = 0; p0 < np; p0 += U) {
+#pragma unroll
+        for (uint32_t u = 0; u < U; ++u) {
+            const uint32_t p = p0 + u;
+            if (p < np) {
+                u32x4 v;
+#pragma unroll
+                for (uint32_t e = 0; e < 4; ++e)
+                    v[e] = static_cast<uint32_t>(S[a[4 * e]]) | (static_cast<uint32_t>(S[a[4 * e + 1]]) << 8) |
+                           (static_cast<uint32_t>(S[a[4 * e + 2]]) << 16) |
+                           (static_cast<uint32_t>(S[a[4 * e + 3]]) << 24);
+                const uint32_t i = i0 + p * RP;
+                if (!INV) {
+                    v ^= b[u];
+                    if (p + U < np)
+                        b[u] = *reinterpret_cast<const VC_GLOBAL u32x4 *>(
+                            Bq + static_cast<uint64_t>(i0 + (p + U) * RP) * rb);
+                }
+                *reinterpret_cast<VC_GLOBAL u32x4 *>(Oq + static_cast<uint64_t>(i) * ostride) = v;
+#pragma unroll
+                for (uint32_t m = 0; m < 16; ++m) {
+                    a[m] += stepA;
+                    if (a[m] >= wrapA) a[m] -= wrapA;
+                }
+            }
         }
     }
 }
 
-constexpr uint32_t kColStrips[] = {4, 8, 16, 32, 64};
+// Column pass for any frame (X row-major): the same strips, staged and
+// gathered in units of G bytes (G = 4 when rows and pointers are 4-byte
+// aligned, else 1).
+template <int SB, int NT, bool INV, int G>
+__global__ __launch_bounds__(NT) void col_shift_g(const FrameDesc *__restrict__ desc, uint32_t first, uint32_t nframes,
+                                                  Geometry geo, uint32_t nstrips, int xcd_map) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    uint32_t fl, strip;
+    map_strip(blockIdx.x, nstrips, xcd_map, fl, strip);
+    if (fl >= nframes) return;
+    const FrameDesc d = desc[first + fl];
+    const uint32_t h = geo.h, rb = geo.row_bytes;
+    const uint32_t k0 = strip * SB;
+    const uint32_t sb = (rb - k0 < static_cast<uint32_t>(SB)) ? rb - k0 : SB;
+    const uint32_t ng = sb / G;  // units per strip row
+    uint8_t *S = smem;           // row stride SB
+    uint32_t *dvS = reinterpret_cast<uint32_t *>(smem + col_dv_off(h, SB));
+    const VC_GLOBAL uint8_t *in = gmem(INV ? d.in : d.X) + k0;
+    VC_GLOBAL uint8_t *out = gmem(INV ? d.X : d.out) + k0;
+    const VC_GLOBAL uint8_t *Bp = gmem(d.B) + k0;
+    col_distances(gmem(d.D), geo, k0, sb, INV, dvS, NT);
+    const uint32_t total = h * ng;
+    for (uint32_t it = threadIdx.x; it < total; it += NT) {
+        const uint32_t i = it / ng, g = it - i * ng;
+        const uint64_t off = static_cast<uint64_t>(i) * rb + G * g;
+        if (G == 4) {
+            uint32_t v = *reinterpret_cast<const VC_GLOBAL uint32_t *>(in + off);
+            if (INV) v ^= *reinterpret_cast<const VC_GLOBAL uint32_t *>(Bp + off);
+            *reinterpret_cast<uint32_t *>(S + i * SB + 4 * g) = v;
+        } else {
+            uint8_t v = in[off];
+            if (INV) v ^= Bp[off];
+            S[i * SB + g] = v;
+        }
+    }
+    __syncthreads();
+    for (uint32_t it = threadIdx.x; it < total; it += NT) {
+        const uint32_t i = it / ng, g = it - i * ng;
+        const uint64_t off = static_cast<uint64_t>(i) * rb + G * g;
+        uint32_t v = 0;
+#pragma unroll
+        for (uint32_t m = 0; m < static_cast<uint32_t>(G); ++m) {
+            const uint32_t kk = G * g + m, dv = dvS[kk];
+            const uint32_t r = (i >= dv) ? i - dv : i + h - dv;
+            v |= static_cast<uint32_t>(S[r * SB + kk]) << (8 * m);
+        }
+        if (G == 4) {
+            if (!INV) v ^= *reinterpret_cast<const VC_GLOBAL uint32_t *>(Bp + off);
+            *reinterpret_cast<VC_GLOBAL uint32_t *>(out + off) = v;
+        } else {
+            if (!INV) v ^= Bp[off];
+            out[off] = static_cast<uint8_t>(v);
+        }
+    }
+}
 
-template <int WT, int NT, bool INV>
-hipError_t launch_col_one(const FrameDesc *d_desc, uint32_t first, uint32_t count, const Geometry &g, bool aligned,
-                          int xcd_map, hipStream_t s) {
-    const uint32_t nstrips = (g.w + WT - 1) / WT;
+constexpr uint32_t kColStrips[] = {4, 8, 16, 32, 64, 128};
+
+template <int SB, int NT, bool INV>
+hipError_t launch_col_one(const FrameDesc *d_desc, uint32_t first, uint32_t count, const Geometry &g, int align,
+                          bool vec, int xcd_map, hipStream_t s) {
+    const uint32_t nstrips = (g.row_bytes + SB - 1) / SB;
     const uint64_t groups =
         xcd_map ? 8ull * ((count + 7) / 8) * nstrips : static_cast<uint64_t>(count) * nstrips;
     if (groups > 0x7FFFFFFFull) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((col_shift<WT, NT, INV>), dim3(static_cast<uint32_t>(groups)), dim3(NT),
-                       ColLayout<WT>::bytes(g.h), s, d_desc, first, count, g, nstrips, xcd_map, aligned ? 1 : 0);
+    const dim3 grid(static_cast<uint32_t>(groups)), block(NT);
+    const uint32_t lds = col_lds_bytes(g.h, SB);
+    if constexpr (SB >= 16) {
+        if (vec) {
+            hipLaunchKernelGGL((col_shift_v<SB, NT, INV>), grid, block, lds, s, d_desc, first, count, g, nstrips,
+                               xcd_map);
+            return hipGetLastError();
+        }
+    }
+    if (align >= 1)
+        hipLaunchKernelGGL((col_shift_g<SB, NT, INV, 4>), grid, block, lds, s, d_desc, first, count, g, nstrips,
+                           xcd_map);
+    else
+        hipLaunchKernelGGL((col_shift_g<SB, NT, INV, 1>), grid, block, lds, s, d_desc, first, count, g, nstrips,
+                           xcd_map);
     return hipGetLastError();
 }
 
-template <int WT, bool INV>
-hipError_t launch_col_wt(const FrameDesc *d_desc, uint32_t first, uint32_t count, const Geometry &g, bool aligned,
-                         const ConfuseTuning &t, hipStream_t s) {
+template <int SB, bool INV>
+hipError_t launch_col_sb(const FrameDesc *d_desc, uint32_t first, uint32_t count, const Geometry &g, int align,
+                         bool vec, const ConfuseTuning &t, hipStream_t s) {
     switch (t.threads) {
-    case 256: return launch_col_one<WT, 256, INV>(d_desc, first, count, g, aligned, t.xcd_map, s);
-    case 512: return launch_col_one<WT, 512, INV>(d_desc, first, count, g, aligned, t.xcd_map, s);
-    default: return launch_col_one<WT, 1024, INV>(d_desc, first, count, g, aligned, t.xcd_map, s);
+    case 256: return launch_col_one<SB, 256, INV>(d_desc, first, count, g, align, vec, t.xcd_map, s);
+    case 512: return launch_col_one<SB, 512, INV>(d_desc, first, count, g, align, vec, t.xcd_map, s);
+    default: return launch_col_one<SB, 1024, INV>(d_desc, first, count, g, align, vec, t.xcd_map, s);
     }
 }
 
 template <bool INV>
-hipError_t launch_col(const FrameDesc *d_desc, uint32_t first, uint32_t count, const Geometry &g, bool aligned,
+hipError_t launch_col(const FrameDesc *d_desc, uint32_t first, uint32_t count, const Geometry &g, int align, bool vec,
                       const ConfuseTuning &t, hipStream_t s) {
     switch (t.strip) {
-    case 4: return launch_col_wt<4, INV>(d_desc, first, count, g, aligned, t, s);
-    case 8: return launch_col_wt<8, INV>(d_desc, first, count, g, aligned, t, s);
-    case 16: return launch_col_wt<16, INV>(d_desc, first, count, g, aligned, t, s);
-    case 32: return launch_col_wt<32, INV>(d_desc, first, count, g, aligned, t, s);
-    case 64: return launch_col_wt<64, INV>(d_desc, first, count, g, aligned, t, s);
+    case 4: return launch_col_sb<4, INV>(d_desc, first, count, g, align, vec, t, s);
+    case 8: return launch_col_sb<8, INV>(d_desc, first, count, g, align, vec, t, s);
+    case 16: return launch_col_sb<16, INV>(d_desc, first, count, g, align, vec, t, s);
+    case 32: return launch_col_sb<32, INV>(d_desc, first, count, g, align, vec, t, s);
+    case 64: return launch_col_sb<64, INV>(d_desc, first, count, g, align, vec, t, s);
+    case 128: return launch_col_sb<128, INV>(d_desc, first, count, g, align, vec, t, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -444,34 +514,39 @@ hipError_t launch_row(const FrameDesc *d_desc, uint32_t first, uint32_t count, c
     return hipGetLastError();
 }
 
-template <int WT, int NT>
-hipError_t set_col_attr(uint32_t limit) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&col_shift<WT, NT, false>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(limit));
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&col_shift<WT, NT, true>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(limit));
+template <typename K>
+hipError_t set_lds(K kernel, uint32_t limit) {
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               static_cast<int>(limit));
 }
 
-template <int WT>
-hipError_t set_col_attr_wt(uint32_t limit) {
-    hipError_t e = set_col_attr<WT, 256>(limit);
-    if (e == hipSuccess) e = set_col_attr<WT, 512>(limit);
-    if (e == hipSuccess) e = set_col_attr<WT, 1024>(limit);
+template <int SB, int NT>
+hipError_t set_col_attr(uint32_t limit) {
+    hipError_t e = set_lds(&col_shift_g<SB, NT, false, 4>, limit);
+    if (e == hipSuccess) e = set_lds(&col_shift_g<SB, NT, true, 4>, limit);
+    if (e == hipSuccess) e = set_lds(&col_shift_g<SB, NT, false, 1>, limit);
+    if (e == hipSuccess) e = set_lds(&col_shift_g<SB, NT, true, 1>, limit);
+    if constexpr (SB >= 16) {
+        if (e == hipSuccess) e = set_lds(&col_shift_v<SB, NT, false>, limit);
+        if (e == hipSuccess) e = set_lds(&col_shift_v<SB, NT, true>, limit);
+    }
+    return e;
+}
+
+template <int SB>
+hipError_t set_col_attr_sb(uint32_t limit) {
+    hipError_t e = set_col_attr<SB, 256>(limit);
+    if (e == hipSuccess) e = set_col_attr<SB, 512>(limit);
+    if (e == hipSuccess) e = set_col_attr<SB, 1024>(limit);
     return e;
 }
 
 }  // namespace
 
 uint32_t shift_col_lds_bytes(uint32_t h, uint32_t strip) {
-    switch (strip) {
-    case 4: return ColLayout<4>::bytes(h);
-    case 8: return ColLayout<8>::bytes(h);
-    case 16: return ColLayout<16>::bytes(h);
-    case 32: return ColLayout<32>::bytes(h);
-    case 64: return ColLayout<64>::bytes(h);
-    default: return 0xFFFFFFFFu;
-    }
+    for (uint32_t sb : kColStrips)
+        if (sb == strip) return col_lds_bytes(h, strip);
+    return 0xFFFFFFFFu;
 }
 
 bool shift_rows_staged(uint32_t w, uint32_t lds_bytes) {
@@ -481,43 +556,50 @@ bool shift_rows_staged(uint32_t w, uint32_t lds_bytes) {
 
 uint32_t shift_max_strip(uint32_t h, uint32_t lds_bytes) {
     uint32_t best = 0;
-    for (uint32_t wt : kColStrips)
-        if (static_cast<uint64_t>(shift_col_lds_bytes(h, wt)) <= lds_bytes) best = wt;
+    for (uint32_t sb : kColStrips)
+        if (static_cast<uint64_t>(col_lds_bytes(h, sb)) <= lds_bytes) best = sb;
     return best;
 }
 
 hipError_t shift_configure(uint32_t lds_limit) {
-    hipError_t e = set_col_attr_wt<4>(lds_limit);
-    if (e == hipSuccess) e = set_col_attr_wt<8>(lds_limit);
-    if (e == hipSuccess) e = set_col_attr_wt<16>(lds_limit);
-    if (e == hipSuccess) e = set_col_attr_wt<32>(lds_limit);
-    if (e == hipSuccess) e = set_col_attr_wt<64>(lds_limit);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&row_shift<false, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_limit));
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&row_shift<true, true>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_limit));
+    hipError_t e = set_col_attr_sb<4>(lds_limit);
+    if (e == hipSuccess) e = set_col_attr_sb<8>(lds_limit);
+    if (e == hipSuccess) e = set_col_attr_sb<16>(lds_limit);
+    if (e == hipSuccess) e = set_col_attr_sb<32>(lds_limit);
+    if (e == hipSuccess) e = set_col_attr_sb<64>(lds_limit);
+    if (e == hipSuccess) e = set_col_attr_sb<128>(lds_limit);
+    if (e == hipSuccess) e = set_lds(&row_shift<false, true>, lds_limit);
+    if (e == hipSuccess) e = set_lds(&row_shift<true, true>, lds_limit);
     return e;
 }
 
+uint32_t shift_xstrip(uint32_t w, uint32_t strip, int align, uint32_t lds_limit) {
+    if (align < 2 || strip < 16 || (3ull * w) % 16 != 0 || !shift_rows_staged(w, lds_limit)) return 0;
+    for (uint32_t sb : kColStrips)
+        if (sb == strip) return strip;
+    return 0;
+}
+
 hipError_t launch_shift(int decrypt, int pass, const FrameDesc *d_desc, uint32_t first, uint32_t count, uint32_t w,
-                        uint32_t h, bool aligned, const ConfuseTuning &t, uint32_t lds_limit, hipStream_t s) {
+                        uint32_t h, int align, const ConfuseTuning &t, uint32_t lds_limit, hipStream_t s) {
     if (count == 0) return hipSuccess;
     Geometry g;
     g.w = w;
     g.h = h;
     g.W8 = 8 * w;
     g.row_bytes = 3 * w;
-    g.inv_h = 1.0f / static_cast<float>(h);
-    g.inv_W8 = 1.0f / static_cast<float>(g.W8);
+    g.mod_h = mod_magic(h);
+    g.mod_W8 = mod_magic(g.W8);
     // encrypt: pass 0 = rows, pass 1 = columns; decrypt: pass 0 = columns, pass 1 = rows
     const bool rows = decrypt ? pass == 1 : pass == 0;
     if (rows)
-        return decrypt ? launch_row<true>(d_desc, first, count, g, aligned, lds_limit, s)
-                       : launch_row<false>(d_desc, first, count, g, aligned, lds_limit, s);
-    return decrypt ? launch_col<true>(d_desc, first, count, g, aligned, t, s)
-                   : launch_col<false>(d_desc, first, count, g, aligned, t, s);
+        return decrypt ? launch_row<true>(d_desc, first, count, g, align >= 1, lds_limit, s)
+                       : launch_row<false>(d_desc, first, count, g, align >= 1, lds_limit, s);
+    // the 16-byte kernels read or write X strip-major in this launch's
+    // strips; the host lays X out so exactly when shift_xstrip says so
+    const bool vec = shift_xstrip(w, t.strip, align, lds_limit) != 0;
+    return decrypt ? launch_col<true>(d_desc, first, count, g, align, vec, t, s)
+                   : launch_col<false>(d_desc, first, count, g, align, vec, t, s);
 }
 
 }  // namespace vc

@@ -84,13 +84,15 @@ def _load() -> C.CDLL:
                                    C.POINTER(vp), C.POINTER(vp), C.POINTER(vp), vp]
     L.vc_debug_keysched.argtypes = [vp, C.c_size_t, C.POINTER(VcShape), u8p, C.POINTER(vp),
                                     C.POINTER(vp), C.POINTER(vp), vp]
+    L.vc_debug_keygen.argtypes = [vp, C.c_size_t, C.POINTER(VcShape), C.POINTER(vp), C.POINTER(vp),
+                                  C.POINTER(vp), vp]
     for name in ("cipher_init", "encrypt_frames", "encrypt_frames_hashed", "decrypt_frames", "vc_hash_frames",
                  "cipher_stream_reset",
                  "cipher_stream_get_state", "cipher_stream_set_state", "cipher_status",
                  "vc_profile_enable", "vc_profile_read", "vc_profile_reset", "vc_set_tuning",
                  "vc_set_overlap", "vc_set_confusion_passes", "vc_autotune",
                  "vc_frame_histograms", "vc_block_histograms", "vc_pair_moments", "vc_frame_diff",
-                 "vc_debug_confuse", "vc_debug_keysched", "vc_key_from_bytes"):
+                 "vc_debug_confuse", "vc_debug_keysched", "vc_debug_keygen", "vc_key_from_bytes"):
         getattr(L, name).restype = C.c_int
     return L
 
@@ -246,6 +248,17 @@ def vc_debug_keysched(ctx: int, shapes_hw: Sequence[Tuple[int, int]], streams: S
     rc = lib.vc_debug_keysched(C.c_void_p(ctx), len(shapes_hw), arr, C.c_void_p(hashes.data_ptr()),
                                _ptrs(IR), _ptrs(D), _ptrs(B), C.c_void_p(_stream_handle(stream)))
     _check(rc, "vc_debug_keysched")
+
+
+def vc_debug_keygen(ctx: int, shapes_hw: Sequence[Tuple[int, int]], IR: Sequence[torch.Tensor],
+                    D: Sequence[torch.Tensor], B: Sequence[torch.Tensor],
+                    stream: Optional[torch.cuda.Stream] = None) -> None:
+    arr = (VcShape * max(len(shapes_hw), 1))()
+    for i, (h, w) in enumerate(shapes_hw):
+        arr[i] = VcShape(w, h, 3, 0, 0)
+    rc = lib.vc_debug_keygen(C.c_void_p(ctx), len(shapes_hw), arr, _ptrs(IR), _ptrs(D), _ptrs(B),
+                             C.c_void_p(_stream_handle(stream)))
+    _check(rc, "vc_debug_keygen")
 
 
 def cipher_stream_reset(ctx: int, stream: int) -> None:
@@ -481,6 +494,15 @@ class Cipher:
         vc_debug_keysched(self.ctx, shapes_hw, streams, self._seqs(streams), hashes, IR, D, B, stream)
         self._advance(streams)
         return IR, D, B
+
+    def keygen(self, shapes_hw: Sequence[Tuple[int, int]], IR: Sequence[torch.Tensor],
+               stream: Optional[torch.cuda.Stream] = None):
+        """Keystream only from given LHCS_m iterates (testing): returns lists D (int16), B (h, w, 3)."""
+        dev = IR[0].device
+        D = [torch.empty(3 * h + 3 * w, dtype=torch.int16, device=dev) for h, w in shapes_hw]
+        B = [torch.empty((h, w, 3), dtype=torch.uint8, device=dev) for h, w in shapes_hw]
+        vc_debug_keygen(self.ctx, shapes_hw, IR, D, B, stream)
+        return D, B
 
     def confuse(self, frames: FrameArg, D: Sequence[torch.Tensor], B: Sequence[torch.Tensor],
                 decrypt: bool = False, stream: Optional[torch.cuda.Stream] = None):

@@ -365,9 +365,10 @@ def test_large_shapes_parity(w, h, n, frames):
 
 @pytest.mark.parametrize("passes", [2, 1])
 def test_extreme_shapes(passes):
-    """The tallest frame the context accepts (a 4-pixel-wide strip of it
-    fills the LDS) against the oracle, one row more rejected, and a single
-    row 65535 pixels wide (the row pass then reads global memory)."""
+    """The tallest frame the context accepts (a strip of 4 bytes per row,
+    two-pass, or of 4 pixels, single pass, fills the LDS) against the oracle,
+    one row more rejected, and a single row 65535 pixels wide (the row pass
+    then reads global memory)."""
     dev = require_gpu()
     Vm = V()
     kb, n = key_bytes(9), 8

@@ -31,6 +31,7 @@ def ctx(request):
     from paper_2505_07158_amd import vcipher as V
     c = V.Cipher(V.vc_key_from_bytes(bytes(range(32)), -1.0, 4))
     c.passes(request.param)
+    c.form = request.param
     yield c
     c.close()
 
@@ -48,13 +49,25 @@ def test_enc_dec_parity(ctx, h, w):
     assert np.array_equal(to_np(Q), P)
 
 
-@pytest.mark.parametrize("strip,threads", list(itertools.product([4, 8, 16, 32, 64], [256, 512, 1024])))
+# Strip widths: bytes of a row for the two-pass form's column pass (4-128),
+# pixels for the single pass (4-64); a strip that the LDS cannot hold at a
+# shape falls back to the automatic choice.  Shapes: ragged strips (52, 68, 30 and
+# 100 columns), 16-byte rows (640, 1280, 1920 columns: the column pass's
+# 16-byte kernels), and the benchmark's 720p and 1080p frames, where 128-byte
+# (two-pass) or 32/64-pixel (single-pass) strips fill most of the LDS.
+TILING_SHAPES = [(37, 52), (64, 68), (29, 30), (50, 100), (480, 640), (720, 1280), (1080, 1920)]
+
+
+@pytest.mark.parametrize("strip,threads", list(itertools.product([4, 8, 16, 32, 64, 128], [256, 512, 1024])))
 def test_every_tiling_gives_the_same_bytes(ctx, strip, threads):
+    if ctx.form == 1 and strip > 64:
+        pytest.skip("single-pass strips are at most 64 pixels")
     dev = torch.device("cuda:0")
     rng = np.random.default_rng(strip * 7 + threads)
-    for (h, w) in [(37, 52), (64, 68), (29, 30), (480, 640)]:
+    for k, (h, w) in enumerate(TILING_SHAPES):
         P, D, B = case(rng, h, w)
-        ctx.tune(strip, threads, xcd_map=(threads != 512))
+        # XCD-local mapping on and off, each for every strip and size
+        ctx.tune(strip, threads, xcd_map=(k + strip // 4 + threads // 256) % 2 == 0)
         try:
             (C,) = ctx.confuse([to_dev(P, dev)], [to_dev(D, dev)], [to_dev(B, dev)])
             (Q,) = ctx.confuse([C], [to_dev(D, dev)], [to_dev(B, dev)], decrypt=True)
@@ -94,7 +107,8 @@ def test_autotuned_tiling_gives_the_same_bytes(ctx):
     h, w = 90, 124
     for decrypt in (False, True):
         strip, threads = ctx.autotune(w, h, frames=4, decrypt=decrypt)
-        assert strip in (4, 8, 16, 32, 64) and threads in (256, 512, 1024)
+        assert strip in ((4, 8, 16, 32, 64, 128) if ctx.form == 2 else (4, 8, 16, 32, 64))
+        assert threads in (256, 512, 1024)
     P, D, B = case(rng, h, w)
     (C,) = ctx.confuse([to_dev(P, dev)], [to_dev(D, dev)], [to_dev(B, dev)])
     assert np.array_equal(to_np(C), oracle.confuse_enc(P, D, B))

@@ -44,3 +44,50 @@ def test_keysched_parity(n, shapes):
         assert nxt == len(shapes)
         assert c.status() == 0
         c.close()
+
+
+@pytest.mark.parametrize("n,shape", [(2, (480, 640)), (1, (480, 640)), (32, (64, 64)), (7, (33, 47))])
+def test_keygen_from_given_iterates(n, shape):
+    """Keystream generation alone (Sec. II-B, Alg. 2) from LHCS_m iterates
+    that the oracle's chain produced: D and B bit-identical."""
+    dev = require_gpu()
+    from paper_2505_07158_amd import vcipher as V
+    kb, gamma = key_bytes(3), -1.0
+    c = V.Cipher(V.vc_key_from_bytes(kb, gamma, n))
+    h, w = shape
+    ir = oracle.chain(oracle.reconstruct(oracle.key_from_bytes(kb), bytes(range(32))), gamma, n)
+    D, B = c.keygen([shape], [to_dev(ir, dev)])
+    d, b = oracle.keystream(ir, gamma, n, w, h)
+    assert np.array_equal(to_np(D[0]), d) and np.array_equal(to_np(B[0]), b)
+    assert c.status() == 0
+    c.close()
+
+
+@pytest.mark.parametrize("n,shape,worker", [(2, (480, 640), 0), (1, (480, 640), 0), (32, (64, 64), 31),
+                                            (7, (33, 47), 3)])
+def test_nonfinite_trajectory_is_reported(n, shape, worker):
+    """A worker seeded with values far outside the attractor overflows within
+    a few RK4 steps.  The oracle rejects the iterates; the library raises its
+    device flag, which cipher_status reports once as VC_ENONFINITE and then
+    clears, and the context keeps working.  (Through encrypt_frames the
+    reconstruction keeps every initial condition below 32 in magnitude, so
+    only caller-supplied iterates reach this path.)"""
+    dev = require_gpu()
+    from paper_2505_07158_amd import vcipher as V
+    kb, gamma = key_bytes(3), -1.0
+    c = V.Cipher(V.vc_key_from_bytes(kb, gamma, n))
+    h, w = shape
+    ir = oracle.chain(oracle.reconstruct(oracle.key_from_bytes(kb), bytes(range(32))), gamma, n)
+    ir[2 * worker:2 * worker + 2] = 1e200
+    with pytest.raises(oracle.OracleError):
+        oracle.keystream(ir, gamma, n, w, h)
+    c.keygen([shape], [to_dev(ir, dev)])
+    assert c.status() == V.VC_ENONFINITE
+    assert c.status() == 0
+    # the context still encrypts correctly afterwards
+    f = np.random.default_rng(5).integers(0, 256, (h, w, 3), dtype=np.uint8)
+    C_, H_ = c.encrypt(to_dev(f[None], dev))
+    Cs, Hs, _ = oracle.encrypt_stream(oracle.key_from_bytes(kb), gamma, n, [f])
+    assert np.array_equal(to_np(C_)[0], Cs[0]) and to_np(H_)[0].tobytes() == Hs[0]
+    assert c.status() == 0
+    c.close()
