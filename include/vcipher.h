@@ -129,6 +129,37 @@ int decrypt_frames(vc_cipher *ctx, size_t count, const uint8_t *const *frames,
                    const vc_shape *shapes, const uint8_t *hashes,
                    uint8_t *const *out, void *stream);
 
+/* Size of the fixed device array (one per GPU the library runs on, held
+ * until the process ends) that encrypt_frames_noalloc works in. */
+#define VC_NOALLOC_SCRATCH_BYTES (64u * 1024u * 1024u)
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc:
+ * encrypt_frames (same arguments, same output bytes, hashes and chain
+ * updates) without any allocation.  The buffers a call needs beyond the
+ * caller's frames, outputs and hashes -- its frame descriptors (the first
+ * 1 MiB) and, per frame, the LHCS_m iterates, distances, keystream and the
+ * two-pass intermediate image -- live in one fixed array of
+ * VC_NOALLOC_SCRATCH_BYTES on the context's GPU instead of the context's
+ * scratch; descriptors are staged through a pinned buffer that cipher_init
+ * set aside.  The call allocates no device or pinned memory and creates no
+ * stream or event; every stage (hash, chain, keystream, confusion) runs on
+ * `stream`, in order, without the chain/keystream overlap of
+ * encrypt_frames.  Frames are taken in spans that fit the array.
+ * Errors, before anything is enqueued: VC_ENOMEM if one frame needs more
+ * than VC_NOALLOC_SCRATCH_BYTES - 1 MiB (vc_scratch_per_frame; every frame
+ * up to 3840x2160 fits), VC_EINVAL if the descriptors of `count` frames
+ * exceed 1 MiB (more than about 9,000 frames), and the errors of
+ * encrypt_frames.  Every call on one GPU shares that GPU's array, which
+ * keeps the last call's contents (no part of it needs to start at zero:
+ * each kernel writes what it later reads): calls that overlap in time on
+ * one GPU -- on different streams, from other contexts or threads -- race
+ * and give wrong results, so the caller serialises them.  Calls of the same
+ * context are ordered with its other calls through events created at
+ * cipher_init.  Profiling (vc_profile_enable) does not time its kernels. */
+int encrypt_frames_noalloc(vc_cipher *ctx, size_t count, const uint8_t *const *frames,
+                           const vc_shape *shapes, uint8_t *hashes, uint8_t *const *out, void *stream);
+
 /* encrypt_frames with the frame hashes already computed (by
  * vc_hash_frames on the same plaintext, possibly on another stream): runs
  * the key schedule and the confusion + XOR only.  hashes (device,

@@ -38,7 +38,36 @@
 
 using namespace vc;
 
+// The allocation-free entry point's device buffer: one per GPU the library
+// runs on, held until the process ends.  Host code must never pass this
+// name to a kernel or a copy (in host code it is a stand-in, not a device
+// address); it uses the address hipGetSymbolAddress returns for the current
+// device (noalloc_base).
+static __device__ __align__(256) uint8_t scratch[VC_NOALLOC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr size_t kNoAllocDesc = size_t(1) << 20;                          // descriptors
+constexpr size_t kNoAllocData = size_t(VC_NOALLOC_SCRATCH_BYTES) - kNoAllocDesc;  // per-frame buffers
+
+std::mutex g_noalloc_mu;
+std::map<int, uint8_t *> g_noalloc_base;  // device -> address of `scratch` on it
+
+// Address of `scratch` on device `dev` (current), resolved once per device.
+hipError_t noalloc_base(int dev, uint8_t **out) {
+    std::lock_guard<std::mutex> lk(g_noalloc_mu);
+    auto it = g_noalloc_base.find(dev);
+    if (it != g_noalloc_base.end()) {
+        *out = it->second;
+        return hipSuccess;
+    }
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return e != hipSuccess ? e : hipErrorInvalidSymbol;
+    g_noalloc_base[dev] = static_cast<uint8_t *>(p);
+    *out = static_cast<uint8_t *>(p);
+    return hipSuccess;
+}
 
 constexpr size_t kDefaultScratch = size_t(2) << 30;
 constexpr uint32_t kMaxN = 1024;
@@ -136,6 +165,17 @@ struct vc_cipher {
     double acc_ms[K_COUNT] = {};
     uint64_t acc_n[K_COUNT] = {};
     hipStream_t last_stream = nullptr;
+    // allocation-free calls (encrypt_frames_noalloc): the device array
+    // `scratch` on this context's GPU, a pinned staging buffer for their
+    // descriptors, and events that order them with the context's other calls
+    uint8_t *na_base = nullptr;
+    uint8_t *na_host = nullptr;
+    hipEvent_t na_stage_ev = nullptr;  // behind the last no-alloc descriptor copy
+    bool na_stage_live = false;
+    hipEvent_t na_wait_ev = nullptr;   // the chain stream's work before a no-alloc call
+    hipEvent_t na_done_ev = nullptr;   // end of the last no-alloc call's chain work
+    bool na_pending = false;           // the chain stream has not waited for na_done_ev yet
+    bool in_noalloc = false;           // set while a no-alloc call runs (no profiling events)
     std::mutex mu;
 };
 
@@ -166,7 +206,7 @@ hipEvent_t take_event(vc_cipher *ctx) {
 // Launch wrapper: records a pair of events around the launch when profiling.
 template <typename F>
 hipError_t timed(vc_cipher *ctx, int kernel, hipStream_t s, F &&launch) {
-    if (!ctx->profile) return launch();
+    if (!ctx->profile || ctx->in_noalloc) return launch();
     hipEvent_t a = take_event(ctx), b = take_event(ctx);
     if (!a || !b) return hipErrorOutOfMemory;
     hipError_t e = hipEventRecord(a, s);
@@ -320,6 +360,7 @@ struct CallArgs {
     uint16_t *const *kD;
     uint8_t *const *kB;
     int decrypt;                  // for DebugConfuse
+    bool noalloc;                 // encrypt_frames_noalloc: buffers in `scratch`, everything on `stream`
     hipStream_t stream;
 };
 
@@ -366,7 +407,8 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         if (a.op == Op::DebugConfuse && (!a.dbgD[f] || !a.dbgB[f])) return VC_EINVAL;
         if ((a.op == Op::DebugKeysched || a.op == Op::DebugKeygen) && (!a.kIR[f] || !a.kD[f] || !a.kB[f]))
             return VC_EINVAL;
-        if (uses_scratch && scratch_need(s, n, keysched_scratch, two_pass) > slot_bytes(ctx)) return VC_ENOMEM;
+        if (uses_scratch && scratch_need(s, n, keysched_scratch, two_pass) > (a.noalloc ? kNoAllocData : slot_bytes(ctx)))
+            return VC_ENOMEM;
         if (uses_chain) {
             if (s.stream >= ctx->max_streams) return VC_EINVAL;
             auto it = seq_next.find(s.stream);
@@ -375,16 +417,22 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
             seq_next[s.stream] = expect + 1;
         }
     }
+    // descriptors of a no-alloc call: frame descriptors, at most one stream
+    // run and one chain record per frame, each table 256-byte aligned
+    if (a.noalloc && align_up(sizeof(FrameDesc) * count, 256) + align_up(sizeof(StreamRun) * count, 256) +
+                             align_up(sizeof(ChainRec) * count, 256) > kNoAllocDesc)
+        return VC_EINVAL;
     if (count == 0) return VC_OK;
-    if (uses_chain || uses_scratch) {
+    if ((uses_chain || uses_scratch) && !a.noalloc) {
         const hipError_t e = ensure_streams(ctx);
         if (e != hipSuccess) return map_err(e);
     }
 
     // ---- plan spans (consecutive frames whose scratch fits a slot) and parts ----
-    const bool overlap = (encrypting || a.op == Op::Decrypt) && ctx->parts > 1;
-    const size_t cap = slot_bytes(ctx);
-    uint8_t *const sbase = ctx->d_scratch;
+    const bool overlap = (encrypting || a.op == Op::Decrypt) && ctx->parts > 1 && !a.noalloc;
+    const size_t cap = a.noalloc ? kNoAllocData : slot_bytes(ctx);
+    // no-alloc: every span reuses the data area of `scratch` in turn (one stream)
+    uint8_t *const sbase = a.noalloc ? ctx->na_base + kNoAllocDesc : ctx->d_scratch;
     struct Part {
         size_t b, e;
         uint32_t span;
@@ -425,7 +473,7 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
     for (size_t pi = 0; pi < parts.size(); ++pi) {
         const Part &pt = parts[pi];
         const std::pair<size_t, size_t> sp{pt.b, pt.e};
-        if (pi == 0 || parts[pi - 1].span != pt.span) off = slot_of(pt.span) * cap;
+        if (pi == 0 || parts[pi - 1].span != pt.span) off = a.noalloc ? 0 : slot_of(pt.span) * cap;
         Chunk ch;
         ch.span = pt.span;
         ch.desc_begin = static_cast<uint32_t>(sp.first);
@@ -525,16 +573,32 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
     const size_t order_bytes = align_up(sizeof(ChainRec) * std::max<size_t>(order.size(), 1), 256);
     const size_t total = desc_bytes + runs_bytes + order_bytes;
     int slot = 0;
-    int rc = stage_acquire(ctx, total, &slot);
-    if (rc) return rc;
-    uint8_t *hs = ctx->h_stage[slot];
+    uint8_t *hs = nullptr, *ds = nullptr;
+    if (a.noalloc) {
+        // the pinned buffer from cipher_init, once the previous no-alloc
+        // call's copy out of it is done; the descriptors go to the head of
+        // `scratch`
+        if (ctx->na_stage_live && hipEventSynchronize(ctx->na_stage_ev) != hipSuccess) return VC_EDEVICE;
+        ctx->na_stage_live = false;
+        hs = ctx->na_host;
+        ds = ctx->na_base;
+    } else {
+        int rc = stage_acquire(ctx, total, &slot);
+        if (rc) return rc;
+        hs = ctx->h_stage[slot];
+        ds = ctx->d_stage[slot];
+    }
     std::memcpy(hs, desc.data(), sizeof(FrameDesc) * count);
     if (!runs.empty()) std::memcpy(hs + desc_bytes, runs.data(), sizeof(StreamRun) * runs.size());
     if (!order.empty()) std::memcpy(hs + desc_bytes + runs_bytes, order.data(), sizeof(ChainRec) * order.size());
     const hipStream_t s = a.stream;
-    uint8_t *ds = ctx->d_stage[slot];
     hipError_t e = hipMemcpyAsync(ds, hs, total, hipMemcpyHostToDevice, s);
     if (e != hipSuccess) return map_err(e);
+    if (a.noalloc) {
+        e = hipEventRecord(ctx->na_stage_ev, s);
+        if (e != hipSuccess) return map_err(e);
+        ctx->na_stage_live = true;
+    }
     const FrameDesc *d_desc = reinterpret_cast<const FrameDesc *>(ds);
     const StreamRun *d_runs = reinterpret_cast<const StreamRun *>(ds + desc_bytes);
     const ChainRec *d_order = reinterpret_cast<const ChainRec *>(ds + desc_bytes + runs_bytes);
@@ -578,14 +642,18 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         if (e != hipSuccess) return map_err(e);
     }
     if (uses_chain) {
-        hipStream_t cs = ctx->chain_stream;
+        // a no-alloc call runs its chain, keygen and confusion on the caller's
+        // stream (no stream or event of its own is created)
+        hipStream_t cs = a.noalloc ? s : ctx->chain_stream;
         // worker streams for keygen + confusion: the side streams, or the
         // chain stream itself when there are none
-        const uint32_t nw = ctx->nside ? ctx->nside : 1;
-        auto wstream = [&](uint32_t k) { return ctx->nside ? ctx->side[k] : cs; };
+        const bool sides = ctx->nside && !a.noalloc;
+        const uint32_t nw = sides ? ctx->nside : 1;
+        auto wstream = [&](uint32_t k) { return sides ? ctx->side[k] : cs; };
         bool used_call[kMaxSide] = {}, used_span[kMaxSide] = {};
         auto release_span = [&](uint32_t span) {
             hipError_t re = hipSuccess;
+            if (a.noalloc) return re;  // `scratch` is not divided into slots
             const uint32_t q = slot_of(span);
             for (uint32_t k = 0; k < nw; ++k) {
                 if (!used_span[k]) continue;
@@ -599,6 +667,7 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         // Makes the caller's stream wait for every worker stream of the call.
         auto join = [&]() {
             hipError_t je = hipSuccess;
+            if (a.noalloc) return je;  // everything ran on the caller's stream
             for (uint32_t k = 0; k < nw; ++k) {
                 if (!used_call[k]) continue;
                 used_call[k] = false;
@@ -614,8 +683,22 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
             (void)join();
             return map_err(err);
         };
-        e = hipEventRecord(ctx->in_ev, s);
-        if (e == hipSuccess) e = hipStreamWaitEvent(cs, ctx->in_ev, 0);
+        if (a.noalloc) {
+            // after the chain work of the context's earlier calls (the chain
+            // states are shared)
+            if (ctx->chain_stream) {
+                e = hipEventRecord(ctx->na_wait_ev, ctx->chain_stream);
+                if (e == hipSuccess) e = hipStreamWaitEvent(s, ctx->na_wait_ev, 0);
+            }
+        } else {
+            e = hipEventRecord(ctx->in_ev, s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(cs, ctx->in_ev, 0);
+            // and after the last no-alloc call's chain work
+            if (e == hipSuccess && ctx->na_pending) {
+                e = hipStreamWaitEvent(cs, ctx->na_done_ev, 0);
+                if (e == hipSuccess) ctx->na_pending = false;
+            }
+        }
         if (e != hipSuccess) return map_err(e);
         for (size_t ci = 0; ci < chunks.size(); ++ci) {
             const Chunk &ch = chunks[ci];
@@ -625,7 +708,7 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
                     if (e != hipSuccess) return fail(e);
                 }
                 cur_span = static_cast<int>(ch.span);
-                if (uses_scratch) {  // wait until the slot's previous user is done with it
+                if (uses_scratch && !a.noalloc) {  // wait until the slot's previous user is done with it
                     const uint32_t q = slot_of(ch.span);
                     for (int k = 0; k < kMaxSide; ++k) {
                         if (!ctx->slot_live[q][k]) continue;
@@ -666,10 +749,16 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         }
         e = join();
         if (e != hipSuccess) return map_err(e);
-        if (uses_scratch) ctx->slot_next = (ctx->slot_next + nspans) % ctx->nslots;
-        // the next call starts on the next side stream, so that the keygen and
-        // confusion of consecutive one-part calls overlap
-        ctx->side_base = static_cast<uint32_t>((ctx->side_base + chunks.size()) % nw);
+        if (a.noalloc) {
+            e = hipEventRecord(ctx->na_done_ev, s);
+            if (e != hipSuccess) return map_err(e);
+            ctx->na_pending = true;
+        } else {
+            if (uses_scratch) ctx->slot_next = (ctx->slot_next + nspans) % ctx->nslots;
+            // the next call starts on the next side stream, so that the keygen and
+            // confusion of consecutive one-part calls overlap
+            ctx->side_base = static_cast<uint32_t>((ctx->side_base + chunks.size()) % nw);
+        }
     } else if (a.op == Op::DebugConfuse) {
         // On the caller's stream; the two-pass intermediate takes scratch
         // slots like any other call.
@@ -704,9 +793,11 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
             ctx->slot_next = (ctx->slot_next + nspans) % ctx->nslots;
         }
     }
-    e = hipEventRecord(ctx->stage_ev[slot], s);
-    if (e != hipSuccess) return map_err(e);
-    ctx->stage_live[slot] = true;
+    if (!a.noalloc) {
+        e = hipEventRecord(ctx->stage_ev[slot], s);
+        if (e != hipSuccess) return map_err(e);
+        ctx->stage_live[slot] = true;
+    }
     ctx->last_stream = s;
     return VC_OK;
 }
@@ -803,6 +894,10 @@ void cipher_destroy(vc_cipher *ctx) {
         }
         if (ctx->chain_stream) (void)hipStreamDestroy(ctx->chain_stream);
         if (ctx->in_ev) (void)hipEventDestroy(ctx->in_ev);
+        if (ctx->na_host) (void)hipHostFree(ctx->na_host);
+        if (ctx->na_stage_ev) (void)hipEventDestroy(ctx->na_stage_ev);
+        if (ctx->na_wait_ev) (void)hipEventDestroy(ctx->na_wait_ev);
+        if (ctx->na_done_ev) (void)hipEventDestroy(ctx->na_done_ev);
         if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
         if (ctx->d_state) (void)hipFree(ctx->d_state);
         if (ctx->d_flags) (void)hipFree(ctx->d_flags);
@@ -851,6 +946,15 @@ int cipher_init(const vc_key *key, uint32_t max_streams, size_t scratch_bytes, v
         e = hipMemcpy(ctx->d_state, st.data(), sizeof(double) * st.size(), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemset(ctx->d_flags, 0, 256);
         for (int k = 0; k < kRing && e == hipSuccess; ++k) e = hipEventCreateWithFlags(&ctx->stage_ev[k], hipEventDisableTiming);
+        // what encrypt_frames_noalloc needs, set up here so that it never
+        // allocates: the address of `scratch` on this device, a pinned
+        // staging buffer for its descriptors and its ordering events
+        if (e == hipSuccess) e = noalloc_base(ctx->device, &ctx->na_base);
+        if (e == hipSuccess)
+            e = hipHostMalloc(reinterpret_cast<void **>(&ctx->na_host), kNoAllocDesc, hipHostMallocDefault);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->na_stage_ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->na_wait_ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&ctx->na_done_ev, hipEventDisableTiming);
         if (e != hipSuccess) { rc = map_err(e); break; }
     } while (false);
     if (rc != VC_OK) {
@@ -881,6 +985,28 @@ int encrypt_frames(vc_cipher *ctx, size_t count, const uint8_t *const *frames, c
     a.out = out;
     a.stream = static_cast<hipStream_t>(stream);
     return locked_call(ctx, a);
+}
+
+int encrypt_frames_noalloc(vc_cipher *ctx, size_t count, const uint8_t *const *frames, const vc_shape *shapes,
+                           uint8_t *hashes, uint8_t *const *out, void *stream) {
+    if (count && (!frames || !shapes || !hashes || !out)) return VC_EINVAL;
+    if (!ctx) return VC_EINVAL;
+    CallArgs a{};
+    a.op = Op::Encrypt;
+    a.noalloc = true;
+    a.count = count;
+    a.in = frames;
+    a.shapes = shapes;
+    a.hashes_out = hashes;
+    a.out = out;
+    a.stream = static_cast<hipStream_t>(stream);
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return VC_EDEVICE;
+    ctx->in_noalloc = true;
+    const int rc = run_call(ctx, a);
+    ctx->in_noalloc = false;
+    return rc;
 }
 
 int decrypt_frames(vc_cipher *ctx, size_t count, const uint8_t *const *frames, const vc_shape *shapes,

@@ -56,6 +56,7 @@ def _load() -> C.CDLL:
     L.cipher_destroy.argtypes = [vp]
     L.cipher_destroy.restype = None
     L.encrypt_frames.argtypes = [vp, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape), u8p, C.POINTER(vp), vp]
+    L.encrypt_frames_noalloc.argtypes = [vp, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape), u8p, C.POINTER(vp), vp]
     L.decrypt_frames.argtypes = [vp, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape), u8p, C.POINTER(vp), vp]
     L.encrypt_frames_hashed.argtypes = [vp, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape), u8p, C.POINTER(vp), vp]
     L.vc_hash_frames.argtypes = [vp, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape), u8p, vp]
@@ -86,7 +87,7 @@ def _load() -> C.CDLL:
                                     C.POINTER(vp), C.POINTER(vp), vp]
     L.vc_debug_keygen.argtypes = [vp, C.c_size_t, C.POINTER(VcShape), C.POINTER(vp), C.POINTER(vp),
                                   C.POINTER(vp), vp]
-    for name in ("cipher_init", "encrypt_frames", "encrypt_frames_hashed", "decrypt_frames", "vc_hash_frames",
+    for name in ("cipher_init", "encrypt_frames", "encrypt_frames_noalloc", "encrypt_frames_hashed", "decrypt_frames", "vc_hash_frames",
                  "cipher_stream_reset",
                  "cipher_stream_get_state", "cipher_stream_set_state", "cipher_status",
                  "vc_profile_enable", "vc_profile_read", "vc_profile_reset", "vc_set_tuning",
@@ -190,6 +191,18 @@ def encrypt_frames(ctx: int, frames: Sequence[torch.Tensor], streams: Sequence[i
     rc = lib.encrypt_frames(C.c_void_p(ctx), len(frames), _ptrs(frames), _shapes(frames, streams, seqs),
                             C.c_void_p(hashes.data_ptr()), _ptrs(out), C.c_void_p(_stream_handle(stream)))
     _check(rc, "encrypt_frames")
+
+
+def encrypt_frames_noalloc(ctx: int, frames: Sequence[torch.Tensor], streams: Sequence[int], seqs: Sequence[int],
+                           hashes: torch.Tensor, out: Sequence[torch.Tensor],
+                           stream: Optional[torch.cuda.Stream] = None) -> None:
+    for t in list(frames) + list(out):
+        _check_frame(t)
+    if hashes.dtype != torch.uint8 or not hashes.is_cuda or hashes.numel() < 32 * len(frames):
+        raise ValueError("hashes must be a CUDA uint8 tensor of count*32 bytes")
+    rc = lib.encrypt_frames_noalloc(C.c_void_p(ctx), len(frames), _ptrs(frames), _shapes(frames, streams, seqs),
+                                    C.c_void_p(hashes.data_ptr()), _ptrs(out), C.c_void_p(_stream_handle(stream)))
+    _check(rc, "encrypt_frames_noalloc")
 
 
 def encrypt_frames_hashed(ctx: int, frames: Sequence[torch.Tensor], streams: Sequence[int], seqs: Sequence[int],
@@ -453,6 +466,15 @@ class Cipher:
         encrypt_frames(self.ctx, fr, streams, self._seqs(streams), hashes, outs, stream)
         self._advance(streams)
         return out, hashes
+
+    def encrypt_noalloc(self, frames: FrameArg, out: FrameArg, hashes: torch.Tensor,
+                        streams: Optional[Sequence[int]] = None,
+                        stream: Optional[torch.cuda.Stream] = None) -> None:
+        """encrypt() through the allocation-free entry point, into caller-given out and hashes."""
+        fr = _frames(frames)
+        streams = list(streams) if streams is not None else [0] * len(fr)
+        encrypt_frames_noalloc(self.ctx, fr, streams, self._seqs(streams), hashes, _frames(out), stream)
+        self._advance(streams)
 
     def encrypt_hashed(self, frames: FrameArg, hashes: torch.Tensor, streams: Optional[Sequence[int]] = None,
                        out: Optional[FrameArg] = None, stream: Optional[torch.cuda.Stream] = None):
