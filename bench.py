@@ -36,6 +36,11 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 VALU_PEAK_GOPS = 256 * 64 * 2.4  # 32-bit lane ops/s (256 CUs x 64 lanes x 2.4 GHz), in G/s
+# FP64 vector: 78.6 TFLOP/s counts a fused multiply-add as two operations;
+# the key schedule's RK4 has no fused operations, so its peak is one FP64
+# operation per lane per clock: 256 CUs x 64 lanes x 2.4 GHz.
+FP64_PEAK_GOPS = 256 * 64 * 2.4
+RK4_FLOPS = 104  # +, -, x of one RK4 step of Eq. 1 in the evaluation order of the key schedule
 
 
 def parse():
@@ -83,6 +88,14 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stats", action="store_true", help="skip the statistics of one ciphertext batch")
+    ap.add_argument("--batched-steps", type=int, default=8,
+                    help="video workload: steps of the batched uneven-shape leg (0 = skip)")
+    ap.add_argument("--serving-seconds", type=float, default=8.0,
+                    help="video workload: seconds of the serving trace leg (0 = skip)")
+    ap.add_argument("--serving-plain-frames", type=int, default=100,
+                    help="video workload: arrivals of the serving leg replayed one frame per launch")
+    ap.add_argument("--ceiling-mb", type=int, default=622,
+                    help="MB per buffer of the streaming copy / xor ceiling (0 = skip)")
     ap.add_argument("--second-n", type=int, default=256, help="worker count of the second row (0 = skip)")
     ap.add_argument("--second-steps", type=int, default=16)
     ap.add_argument("--unpipelined-steps", type=int, default=4, help="steps of the reference without the pipeline")
@@ -131,12 +144,41 @@ def measured_traffic(frames_per_launch: float, w: int, h: int) -> dict:
     return out
 
 
+def run_leg_children(args) -> dict:
+    """Runs `bench.py --workload batched` and `--workload serving` (short) as
+    child processes and returns their JSON lines (or an error record)."""
+    import subprocess
+    out = {}
+    jobs = []
+    if args.batched_steps:
+        jobs.append(("batched", ["--workload", "batched", "--steps", str(args.batched_steps), "--warmup", "2",
+                                 "--n", str(args.n)]))
+    if args.serving_seconds:
+        jobs.append(("serving", ["--workload", "serving", "--duration", str(args.serving_seconds),
+                                 "--plain-frames", str(args.serving_plain_frames), "--n", str(args.n)]))
+    for name, extra in jobs:
+        print(f"bench: {name} leg (child process)", file=sys.stderr, flush=True)
+        try:
+            r = subprocess.run([sys.executable, os.path.abspath(__file__), *extra], capture_output=True, text=True,
+                               timeout=300)
+            lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+            out[name] = json.loads(lines[-1]) if r.returncode == 0 and lines else \
+                {"error": f"exit {r.returncode}", "stderr_tail": r.stderr[-800:]}
+        except subprocess.TimeoutExpired:
+            out[name] = {"error": "timed out after 300 s"}
+    return out
+
+
 def pct(xs, q):
     import numpy as np
     return float(np.percentile(np.asarray(xs, dtype=float), q))
 
 
 def run_serving(args) -> None:
+    print(json.dumps(serving_run(args, args.duration, args.plain_frames)), flush=True)
+
+
+def serving_run(args, duration: float, plain_frames: int) -> dict:
     """Serving workload: 64 streams (seed 5000) with frame rates from
     {24, 30, 60} and resolutions from {640x480, 1280x720, 1920x1080,
     3840x2160}; Poisson arrivals at each stream's frame rate for
@@ -169,7 +211,7 @@ def run_serving(args) -> None:
     trace = []
     for s, st in enumerate(streams):
         t, seq = float(rng.exponential(1.0 / st["fps"])), 0
-        while t < args.duration:
+        while t < duration:
             trace.append((t, s, seq))
             seq += 1
             t += float(rng.exponential(1.0 / st["fps"]))
@@ -265,6 +307,20 @@ def run_serving(args) -> None:
         wait = np.array([1000.0 * (r.launched - r.arrival) for r in reqs])     # queued on the host
         serv = np.array([1000.0 * (r.done - r.launched) for r in reqs])        # first launch to completion
         late = np.array([1000.0 * r.latency > 1000.0 / streams[r.stream]["fps"] for r in reqs])
+        # delay rate (frames later than one frame interval, Sec. V) per FPS
+        # class and per stream
+        per_fps = {}
+        for fps in fps_set:
+            sel = [k for k, r in enumerate(reqs) if streams[r.stream]["fps"] == fps]
+            if sel:
+                per_fps[str(fps)] = {"frames": len(sel), "p50_ms": round(float(np.percentile(lat[sel], 50)), 3),
+                                     "p99_ms": round(float(np.percentile(lat[sel], 99)), 3),
+                                     "delay_rate": round(float(late[sel].mean()), 4)}
+        by_stream = {}
+        for k, r in enumerate(reqs):
+            by_stream.setdefault(r.stream, []).append(k)
+        per_stream = [[s_, streams[s_]["fps"], f"{streams[s_]['w']}x{streams[s_]['h']}", streams[s_]["kind"],
+                       len(ks), round(float(late[ks].mean()), 4)] for s_, ks in sorted(by_stream.items())]
         per_res = {}
         for (w, h) in res_set:
             sel = [k for k, r in enumerate(reqs) if (streams[r.stream]["w"], streams[r.stream]["h"]) == (w, h)]
@@ -279,7 +335,11 @@ def run_serving(args) -> None:
         sizes = [b for _, b in sched.batches]
         return {"frames": len(reqs), "wall_s": round(wall, 3), "frames_per_s": round(len(reqs) / wall, 1),
                 "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                "delay_rate": round(float(late.mean()), 4), "per_resolution": per_res, "batches": len(sizes),
+                "delay_rate": round(float(late.mean()), 4), "per_resolution": per_res, "per_fps": per_fps,
+                "per_stream": {"columns": ["stream", "fps", "resolution", "kind", "frames", "delay_rate"],
+                               "rows": per_stream,
+                               "streams_with_late_frames": int(sum(1 for x in per_stream if x[5] > 0))},
+                "batches": len(sizes),
                 "mean_batch": round(float(np.mean(sizes)), 2), "max_batch_seen": int(max(sizes)),
                 "decrypt_check_ok": bool(ok), "status_ok": bool(status_ok),
                 "host_ms_per_batch": round(1000.0 * host_launch_s / max(len(sizes), 1), 3)}
@@ -291,20 +351,20 @@ def run_serving(args) -> None:
     batched = one_run(trace, args.max_batch, infl, bool(args.hash_first))
     # The plain per-frame path cannot keep up with the offered load; it runs
     # the first --plain-frames arrivals of the same trace.
-    plain = one_run(trace[:args.plain_frames], 1, lambda kind, c: 1, False)
-    offered = len(trace) / args.duration
+    plain = one_run(trace[:plain_frames], 1, lambda kind, c: 1, False)
+    offered = len(trace) / duration
     line = {"metric": "serving: p50/p99 arrival-to-completion latency (ms), frames/s", "value": batched["p99_ms"],
             "unit": "ms (p99)", "n_gpus": 1, "higher_is_better": False, "dtype": "u8", "data": "synthetic",
             "config": {"workload": f"serving, {S} streams, Poisson arrivals at 24/30/60 FPS, resolutions "
                                    "640x480/1280x720/1920x1080/3840x2160, 30% decrypt streams, "
-                                   f"{args.duration} s trace", "n": n, "offered_frames_per_s": round(offered, 1),
+                                   f"{duration} s trace", "n": n, "offered_frames_per_s": round(offered, 1),
                        "hbm_budget_gb": args.hbm_budget_gb, "max_batch": args.max_batch,
                        "inflight_batches_per_kind_and_resolution": f"{args.inflight} ({infl4k} at 3840x2160)",
                        "batch_class": "resolution", "hash_first": bool(args.hash_first),
                        "parts": args.serve_parts, "side_streams": args.serve_side,
                        "side_streams_1080p": args.serve_side_1080p},
             "continuous_batching": batched, "plain_per_frame": plain}
-    print(json.dumps(line), flush=True)
+    return line
 
 
 def run_robustness(args) -> None:
@@ -388,6 +448,10 @@ def run_robustness(args) -> None:
 
 
 def run_batched(args) -> None:
+    print(json.dumps(batched_run(args, args.steps, args.warmup)), flush=True)
+
+
+def batched_run(args, steps: int, warmup: int) -> dict:
     """Batched uneven shapes: 48 streams, 16 each at 640x480, 1280x720 and
     1920x1080, 8 frames per stream per batch (384 frames, 1.27 GB of
     plaintext).  One step encrypts one batch in one call and decrypts it in
@@ -450,12 +514,12 @@ def run_batched(args) -> None:
     torch.cuda.synchronize()
     c0 = [x.clone() for x in cbuf[0]]
     k = 1
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         step(k)
         k += 1
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step(k)
         k += 1
     torch.cuda.synchronize()
@@ -477,18 +541,82 @@ def run_batched(args) -> None:
     ok1 = all(torch.equal(p1[i], frames[i]) for i in range(NF))
     same = all(torch.equal(c1[i], c0[i]) for i in range(NF))  # batch 0 of the batched run: same frames and seqs
     assert enc.status() == 0 and dec.status() == 0
-    line = {"metric": "batched uneven shapes: frames/s (encrypt + decrypt)", "value": round(NF * args.steps / el, 1),
-            "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-            "ms_per_step": round(1000 * el / args.steps, 3), "higher_is_better": True, "dtype": "u8",
+
+    # ---- the same batches as prepared batches (vc_batch_prepare), launched
+    # from HIP graphs.  Two sets of ciphertext and hash buffers; graph j
+    # holds, on two forked capture streams, the encrypt launch into set j and
+    # the decrypt launch of set 1 - j (encrypted by the previous replay), so
+    # that sender and receiver overlap as in the call path above.  Replaying
+    # graph 1, 0, 1, 0, ... after one eager encrypt into set 0 encrypts block
+    # k + 1 while block k is decrypted; every kernel is a launch from the
+    # graph (no host work per batch).
+    eg = V.Cipher.from_bytes(kb, gamma, n, max_streams=len(shapes))
+    dg = V.Cipher.from_bytes(kb, gamma, n, max_streams=len(shapes))
+    for (w, h) in sorted(set(shapes)):
+        for c_, dd in ((eg, False), (dg, True)):
+            c_.autotune(w, h, frames=F * 16, decrypt=dd)
+    gseqs = [f % F for f in range(NF)]
+    cg = [[torch.empty_like(x) for x in frames] for _ in range(2)]
+    pg = [torch.empty_like(x) for x in frames]
+    hg = [torch.empty((NF, 32), dtype=torch.uint8, device=dev) for _ in range(2)]
+    eb = [V.Batch(eg.ctx, False, frames, sids, gseqs, hg[j], cg[j]) for j in range(2)]
+    db = [V.Batch(dg.ctx, True, cg[j], sids, gseqs, hg[j], pg) for j in range(2)]
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    eb[0].launch(sa)                         # eager: block 0 (frames 0..7 of every stream) into set 0
+    torch.cuda.synchronize()
+    graph_same = all(torch.equal(cg[0][i], c0[i]) for i in range(NF)) and torch.equal(hg[0], hbuf[0])
+    graphs = []
+    for j in range(2):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=sa):
+            fork = torch.cuda.Event()
+            fork.record(sa)
+            sb.wait_event(fork)
+            eb[j].launch(sa)
+            db[1 - j].launch(sb)
+            join = torch.cuda.Event()
+            join.record(sb)
+            sa.wait_event(join)
+        graphs.append(g)
+    graph_rt = True
+    r = 0
+    for _ in range(warmup):
+        graphs[(r + 1) % 2].replay()         # encrypt block r + 1, decrypt block r
+        r += 1
+    torch.cuda.synchronize()
+    graph_rt = graph_rt and all(torch.equal(pg[i], frames[i]) for i in range(NF))
+    t2 = time.perf_counter()
+    for _ in range(steps):
+        graphs[(r + 1) % 2].replay()
+        r += 1
+    torch.cuda.synchronize()
+    el2 = time.perf_counter() - t2
+    graph_rt = graph_rt and all(torch.equal(pg[i], frames[i]) for i in range(NF))
+    assert eg.status() == 0 and dg.status() == 0
+    graph = {"value": round(NF * steps / el2, 1), "unit": "frames/s", "steps": steps,
+             "ms_per_step": round(1000 * el2 / steps, 3), "first_launch_equals_call_path": bool(graph_same),
+             "roundtrip_ok": bool(graph_rt), "speedup_vs_plain": round((NF * steps / el2) / (NF / el1), 2),
+             "mode": "vc_batch_prepare once per direction and buffer set; two HIP graphs, each an encrypt batch "
+                     "launch and, on a forked capture stream, the decrypt launch of the previous block; a replay "
+                     "encrypts the next 8 frames of every stream and decrypts the 8 before"}
+    del graphs
+    for b2 in eb + db:
+        b2.close()
+    eg.close(); dg.close()
+
+    line = {"metric": "batched uneven shapes: frames/s (encrypt + decrypt)", "value": round(NF * steps / el, 1),
+            "unit": "frames/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
+            "ms_per_step": round(1000 * el / steps, 3), "higher_is_better": True, "dtype": "u8",
             "data": "synthetic", "config": {"workload": "48 streams (16 x 640x480, 16 x 1280x720, 16 x 1920x1080), "
                                             "8 frames per stream per batch, one encrypt_frames + one decrypt_frames "
                                             "call per batch", "n": n, "frames_per_batch": NF},
             "plain_per_frame": {"value": round(NF / el1, 1), "unit": "frames/s", "calls": 2 * NF},
-            "speedup_vs_plain": round((NF * args.steps / el) / (NF / el1), 2),
-            "roundtrip_ok": bool(ok and ok1), "plain_equals_batched": bool(same),
+            "speedup_vs_plain": round((NF * steps / el) / (NF / el1), 2),
+            "roundtrip_ok": bool(ok and ok1), "plain_equals_batched": bool(same), "graph": graph,
             "autotuned": {"column_pass": tuned, "frames_per_workgroup": "one full-height strip of one frame",
                           "mapping": "XCD-local (all strips of a frame on one XCD)"}}
-    print(json.dumps(line), flush=True)
+    enc.close(); dec.close(); e1.close(); d1.close()
+    return line
 
 
 def main():
@@ -498,6 +626,14 @@ def main():
         print("bench.py measures one GPU only: this build has no multi-GPU path (streams would shard "
               "across GPUs with no collective; see the design notes).  Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
+    # The batched and serving legs of the default run go first, each in a
+    # child process of its own (before this process touches the GPU): the
+    # serving loop wants 32 hardware queues, and in a process that also ran
+    # the pipelined benchmark's contexts that many queues slowed every
+    # multi-call workload several times over.
+    legs = {}
+    if args.workload == "video":
+        legs = run_leg_children(args)
     if args.workload == "serving" and args.hw_queues == 16:
         args.hw_queues = 32     # 8 contexts x (1 + side) streams + 8 x inflight device streams + the null stream
     if args.hw_queues:
@@ -740,6 +876,9 @@ def main():
         return roof
 
     two_pass = "col_shift_xor_enc" in kernels
+    form = ("two-pass confusion + XOR: a row pass (6 B/px moved) then a column pass fused with the XOR "
+            "(9 B/px moved); achieved = the operation's 9 B/px over the two kernels' summed launch times"
+            if two_pass else "single-pass confusion + XOR kernel, 9 B/px")
     if two_pass:
         roof_enc = hbm_roof(["row_shift_enc", "col_shift_xor_enc"], 9.0 * w * h)
         roof_dec = hbm_roof(["col_shift_xor_dec", "row_shift_dec"], 9.0 * w * h)
@@ -752,6 +891,8 @@ def main():
         roof_dec = hbm_roof(["confuse_xor_dec"], 9.0 * w * h)
         roof_kernels = []
         roof_iso = hbm_roof(["confuse_xor_enc"], 9.0 * w * h, kernels_iso, kernels_iso["confuse_xor_enc"]["launches"])
+    for r_ in (roof_enc, roof_dec, roof_iso):
+        r_["form"] = form
 
     # SHA-256: algorithmic 32-bit operations of FIPS 180-4 per 64-byte block
     # (rounds: Sigma1 5, Ch 3, T1 4 adds, Sigma0 5, Maj 4, T2 1, e 1, a 1 =
@@ -766,6 +907,30 @@ def main():
                 "parallelism_limit": f"n={n} serial SHA-256 chains per frame x {T} frames = {n * T} lanes",
                 "max_blocks_per_lane": max(((sub[i + 1] - sub[i]) + 9 + 63) // 64 for i in range(n))}
     dominant = max(kernels, key=lambda k: kernels[k]["total_ms"])
+
+    # Key schedule (lhcs_keygen): algorithmic FP64 operations of Sec. II-B --
+    # every worker advances its two LHCSs by ceil((2 nd_i + nb_i) / 24)
+    # RK4 steps of 104 +, -, x each (the kernel issues 96: eight exact
+    # doublings ride in fused adds).  Its peak is the chip's
+    # FP64 issue rate; the kernel is bound by the serial chain of each worker
+    # (n workers per frame), so the fraction shows how far latency, not
+    # throughput, sets its time.
+    ND = 3 * h + 3 * w
+    kg_steps = [(2 * (ND * (i + 1) // n - ND * i // n) + (L * (i + 1) // n - L * i // n) + 23) // 24
+                for i in range(n)]
+    kg_flops = 2 * RK4_FLOPS * sum(kg_steps)
+
+    def fp64_roof(table, frames_per_launch):
+        kk = table["lhcs_keygen"]
+        g = frames_per_launch * kg_flops / (kk["avg_us"] * 1e-6) / 1e9
+        return {"kernel": "lhcs_keygen", "bound": "alu", "achieved": round(g, 1), "peak": FP64_PEAK_GOPS,
+                "unit": "GFLOP/s (FP64, unfused)", "frac": round(g / FP64_PEAK_GOPS, 4),
+                "flops_per_frame": kg_flops, "frames_per_launch": frames_per_launch,
+                "max_steps_per_worker": max(kg_steps),
+                "parallelism_limit": f"n={n} workers x 2 LHCS per frame, each a serial chain of up to "
+                                     f"{max(kg_steps)} RK4 steps"}
+    roof_keygen = fp64_roof(kernels, 2.0 * T * args.steps / kernels["lhcs_keygen"]["launches"])
+    roof_keygen_iso = fp64_roof(kernels_iso, 2.0 * T / kernels_iso["lhcs_keygen"]["launches"])
 
     # ---- second worker count (n = 256): same workload, timing only ----
     second = None
@@ -901,6 +1066,66 @@ def main():
                               "inside (7.901515798, 7.903422936); timings are host wall clock of synchronous "
                               "calls"}
 
+    # The benchmark's own contexts are done; free their scratch before the
+    # other legs.
+    enc.close()
+    dec.close()
+
+    # ---- streaming ceiling of this GPU: the library's reference copy and
+    # xor kernels (one 16-byte word per thread) over buffers of the size of
+    # one confusion launch's frames ----
+    ceiling = None
+    if args.ceiling_mb:
+        nbytes = args.ceiling_mb * 1000000 // 16 * 16
+        bufs = [torch.empty(nbytes, dtype=torch.uint8, device=dev) for _ in range(3)]
+        for t_ in bufs[:2]:
+            t_.random_(0, 256)
+        rates = {}
+        for kind, name, moved in ((0, "copy", 2), (1, "xor", 3)):
+            for _ in range(2):
+                V.vc_bandwidth_probe(kind, bufs[0], bufs[1], bufs[2])
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            for _ in range(10):
+                V.vc_bandwidth_probe(kind, bufs[0], bufs[1], bufs[2])
+            ev1.record()
+            torch.cuda.synchronize()
+            rates[name] = moved * nbytes * 10 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+        ok_x = bool(torch.equal(bufs[2][:4096], bufs[0][:4096] ^ bufs[1][:4096]))
+        del bufs
+        ceiling = {"copy_GBs": round(rates["copy"], 1), "xor_GBs": round(rates["xor"], 1),
+                   "bytes_per_buffer": nbytes, "xor_ok": ok_x,
+                   "note": "vc_bandwidth_probe, one 16-byte word per thread; copy moves 2 bytes per byte of "
+                           "buffer, xor 3 (two reads, one write: the confusion's access mix)"}
+        for r_ in [roof_enc, roof_dec, roof_iso] + roof_kernels:
+            r_["frac_of_xor_ceiling"] = round(r_["achieved"] / rates["xor"], 4)
+
+    # ---- batched uneven shapes (48 streams, three resolutions) and a short
+    # serving trace: the child processes' lines, condensed ----
+    batched_leg = None
+    b_ = legs.get("batched")
+    if b_ is not None:
+        batched_leg = b_ if "error" in b_ else {k_: b_[k_] for k_ in (
+            "value", "unit", "steps", "ms_per_step", "plain_per_frame", "speedup_vs_plain", "roundtrip_ok",
+            "plain_equals_batched", "graph", "autotuned") if k_ in b_}
+        if "error" not in b_:
+            batched_leg["workload"] = b_["config"]["workload"]
+    serving_leg = None
+    sv = legs.get("serving")
+    if sv is not None:
+        if "error" in sv:
+            serving_leg = sv
+        else:
+            cb = sv["continuous_batching"]
+            serving_leg = {"workload": sv["config"]["workload"],
+                           "offered_frames_per_s": sv["config"]["offered_frames_per_s"], "frames": cb["frames"],
+                           "frames_per_s": cb["frames_per_s"], "p50_ms": cb["p50_ms"], "p99_ms": cb["p99_ms"],
+                           "delay_rate": cb["delay_rate"], "per_resolution": cb["per_resolution"],
+                           "per_fps": cb["per_fps"], "per_stream": cb["per_stream"], "mean_batch": cb["mean_batch"],
+                           "decrypt_check_ok": cb["decrypt_check_ok"], "status_ok": cb["status_ok"],
+                           "plain_per_frame": {k_: sv["plain_per_frame"][k_] for k_ in ("frames", "frames_per_s",
+                                                                                       "p50_ms", "p99_ms")}}
+
     # ---- CPU oracle on this host (bounded sample, same chain as step 1) ----
     cpu = None
     verified = None
@@ -968,6 +1193,9 @@ def main():
         "kernels_isolated": kernels_iso,
         "dispatch_window": dispatch_window,
         "roofline_sha": roof_sha,
+        "roofline_keygen": roof_keygen,
+        "roofline_keygen_isolated": roof_keygen_iso,
+        "ceiling": ceiling,
         "dominant_kernel": dominant,
         "kernels": {k: {kk: (round(vv, 4) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kernels.items()},
@@ -979,6 +1207,8 @@ def main():
         "unpipelined": unpiped,
         "plain_per_frame": plain_pf,
         "statistics": statistics,
+        "batched": batched_leg,
+        "serving": serving_leg,
         "cpu_baseline": cpu,
         "roundtrip_ok": roundtrip_ok,
         "oracle_verified_sample": verified,

@@ -344,6 +344,52 @@ uint32_t vc_max_frame_height(const vc_cipher *ctx);
 int vc_frame_diff(size_t count, const uint8_t *const *a, const uint8_t *const *b, const vc_shape *shapes,
                   uint64_t *out, void *stream);
 
+/* ---- Prepared batches: launch-only calls for HIP graph capture ----
+ * encrypt_frames / decrypt_frames plan every call on the host (shape
+ * groups, scratch spans, chain records), stage its descriptors through a
+ * pinned ring and fork to the context's streams.  A prepared batch does the
+ * planning once: vc_batch_prepare fixes the frames' device buffers, shapes,
+ * streams, hash and output buffers, allocates the batch's own scratch and
+ * uploads its descriptors to device memory the batch owns.
+ * vc_batch_launch then only enqueues kernels on `stream` (the same kernels
+ * as encrypt_frames / decrypt_frames, one after another, without the
+ * chain/keystream overlap of encrypt_frames) -- no copy, no allocation, no
+ * event, no synchronisation -- so one or more launches can be captured in a
+ * HIP graph and the graph replayed; a caller overlaps batches by capturing
+ * launches of different batches on forked streams.
+ *
+ * Every launch, and every replay of a graph that captured one, processes
+ * the frames then in the batch's input buffers as the next frames of their
+ * streams, in the order of `shapes`: the chain states on the device advance
+ * (Sec. II-A: each frame's key material starts from the previous frame's
+ * iterates).  shapes[f].seq only orders the frames of one stream inside the
+ * batch (strictly increasing per stream, else VC_EORDER).  A direct
+ * vc_batch_launch advances the context's host-side sequence numbers of the
+ * batch's streams (cipher_stream_get_state); a graph replay does not.  The
+ * caller orders a context's batch launches with its other calls (they share
+ * its chain states), keeps every buffer alive while the batch exists, and
+ * must not prepare a batch while another call of the context may be
+ * running.  decrypt = 0: frames are plaintext, hashes (device, count*32)
+ * receive H; decrypt = 1: frames are ciphertext, hashes hold the sender's
+ * H.  Tiling (autotuned or fixed) is taken at prepare time.  Kernel
+ * profiling does not time batch launches.  Errors: as encrypt_frames, plus
+ * VC_ENOMEM if the batch's scratch cannot be allocated. */
+typedef struct vc_batch vc_batch;
+int vc_batch_prepare(vc_cipher *ctx, int decrypt, size_t count, const uint8_t *const *frames,
+                     const vc_shape *shapes, uint8_t *hashes, uint8_t *const *out, vc_batch **batch);
+int vc_batch_launch(vc_batch *batch, void *stream);
+/* Frees the batch (synchronises its device first).  NULL is a no-op. */
+void vc_batch_destroy(vc_batch *batch);
+
+/* vc_bandwidth_probe: a measurement helper outside the cipher -- the
+ * streaming ceiling that the confusion kernels' HBM rates are compared with.
+ * kind 0 copies `bytes` from a to out; kind 1 writes out = a ^ b (two reads
+ * and one write per byte, the access mix of the confusion's 9 bytes per
+ * pixel).  One 16-byte word per thread, asynchronous on `stream`.  bytes a
+ * multiple of 16 and every pointer 16-byte aligned (device memory), else
+ * VC_EINVAL. */
+int vc_bandwidth_probe(int kind, const uint8_t *a, const uint8_t *b, uint8_t *out, size_t bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -383,56 +383,24 @@ hipError_t ensure_streams(vc_cipher *ctx) {
 
 size_t slot_bytes(const vc_cipher *ctx) { return ctx->scratch_bytes / ctx->nslots / 256 * 256; }
 
-int run_call(vc_cipher *ctx, const CallArgs &a) {
-    const bool encrypting = a.op == Op::Encrypt || a.op == Op::EncryptHashed;
-    const bool uses_chain = encrypting || a.op == Op::Decrypt || a.op == Op::DebugKeysched;
-    const bool keysched_scratch = encrypting || a.op == Op::Decrypt;
-    const bool two_pass = ctx->passes == 2 && a.op != Op::Hash && a.op != Op::DebugKeysched;
-    const bool uses_scratch = keysched_scratch || two_pass;
-    const int dec_kernel = (a.op == Op::Decrypt) || (a.op == Op::DebugConfuse && a.decrypt);
-    const uint32_t n = ctx->key.n;
+// A call's work, planned on the host: spans of consecutive frames whose
+// scratch fits `cap` bytes (span j's buffers start at span_base(j)), each
+// cut into up to `nparts` parts in call order; per part the frame
+// descriptors grouped by shape and alignment class, and the per-stream runs
+// of chain records.
+struct Plan {
+    std::vector<FrameDesc> desc;
+    std::vector<StreamRun> runs;
+    std::vector<ChainRec> order;
+    std::vector<Chunk> chunks;
+    uint32_t nspans = 0;
+};
+
+template <typename SpanBase>
+void build_plan(const vc_cipher *ctx, const CallArgs &a, bool keysched_scratch, bool two_pass, bool uses_chain,
+                bool uses_scratch, int dec_kernel, uint64_t cap, size_t nparts, SpanBase span_base, Plan &P) {
     const size_t count = a.count;
-
-    // ---- validation (nothing enqueued yet) ----
-    std::map<uint32_t, uint64_t> seq_next;
-    for (size_t f = 0; f < count; ++f) {
-        const vc_shape &s = a.shapes[f];
-        int rc = check_shape(ctx, s, dec_kernel, a.op != Op::DebugConfuse);
-        if (rc) return rc;
-        const uint64_t L = frame_bytes(s);
-        if (a.op != Op::DebugKeysched && a.op != Op::DebugKeygen && !a.in[f]) return VC_EINVAL;
-        if ((encrypting || a.op == Op::Decrypt || a.op == Op::DebugConfuse) && !a.out[f]) return VC_EINVAL;
-        if ((encrypting || a.op == Op::DebugConfuse || a.op == Op::Decrypt) && overlaps(a.in[f], L, a.out[f], L))
-            return VC_EINVAL;
-        if (a.op == Op::DebugConfuse && (!a.dbgD[f] || !a.dbgB[f])) return VC_EINVAL;
-        if ((a.op == Op::DebugKeysched || a.op == Op::DebugKeygen) && (!a.kIR[f] || !a.kD[f] || !a.kB[f]))
-            return VC_EINVAL;
-        if (uses_scratch && scratch_need(s, n, keysched_scratch, two_pass) > (a.noalloc ? kNoAllocData : slot_bytes(ctx)))
-            return VC_ENOMEM;
-        if (uses_chain) {
-            if (s.stream >= ctx->max_streams) return VC_EINVAL;
-            auto it = seq_next.find(s.stream);
-            const uint64_t expect = (it == seq_next.end()) ? ctx->next_seq[s.stream] : it->second;
-            if (s.seq != expect) return VC_EORDER;
-            seq_next[s.stream] = expect + 1;
-        }
-    }
-    // descriptors of a no-alloc call: frame descriptors, at most one stream
-    // run and one chain record per frame, each table 256-byte aligned
-    if (a.noalloc && align_up(sizeof(FrameDesc) * count, 256) + align_up(sizeof(StreamRun) * count, 256) +
-                             align_up(sizeof(ChainRec) * count, 256) > kNoAllocDesc)
-        return VC_EINVAL;
-    if (count == 0) return VC_OK;
-    if ((uses_chain || uses_scratch) && !a.noalloc) {
-        const hipError_t e = ensure_streams(ctx);
-        if (e != hipSuccess) return map_err(e);
-    }
-
-    // ---- plan spans (consecutive frames whose scratch fits a slot) and parts ----
-    const bool overlap = (encrypting || a.op == Op::Decrypt) && ctx->parts > 1 && !a.noalloc;
-    const size_t cap = a.noalloc ? kNoAllocData : slot_bytes(ctx);
-    // no-alloc: every span reuses the data area of `scratch` in turn (one stream)
-    uint8_t *const sbase = a.noalloc ? ctx->na_base + kNoAllocDesc : ctx->d_scratch;
+    const uint32_t n = ctx->key.n;
     struct Part {
         size_t b, e;
         uint32_t span;
@@ -454,26 +422,29 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         spans.push_back({b, count});
         for (size_t si = 0; si < spans.size(); ++si) {
             const size_t sb = spans[si].first, len = spans[si].second - sb;
-            const size_t np = overlap ? std::min<size_t>(ctx->parts, len) : 1;
+            const size_t np = std::max<size_t>(1, std::min<size_t>(nparts, len));
             for (size_t k = 0; k < np; ++k)
                 parts.push_back({sb + len * k / np, sb + len * (k + 1) / np, static_cast<uint32_t>(si)});
         }
     }
 
-    // ---- build descriptors, runs and chain records ----
-    std::vector<FrameDesc> desc(count);
-    std::vector<StreamRun> runs;
-    std::vector<ChainRec> order;
-    std::vector<Chunk> chunks;
+    // descriptors, runs and chain records
+    std::vector<FrameDesc> &desc = P.desc;
+    std::vector<StreamRun> &runs = P.runs;
+    std::vector<ChainRec> &order = P.order;
+    std::vector<Chunk> &chunks = P.chunks;
+    desc.assign(count, FrameDesc{});
     std::vector<uint32_t> desc_of(count);
-    // span j of this call uses scratch slot (slot_next + j) mod nslots
-    const uint32_t nspans = parts.empty() ? 0 : parts.back().span + 1;
-    auto slot_of = [&](uint32_t span) { return (ctx->slot_next + span) % ctx->nslots; };
+    P.nspans = parts.empty() ? 0 : parts.back().span + 1;
+    uint8_t *sbase = nullptr;
     uint64_t off = 0;
     for (size_t pi = 0; pi < parts.size(); ++pi) {
         const Part &pt = parts[pi];
         const std::pair<size_t, size_t> sp{pt.b, pt.e};
-        if (pi == 0 || parts[pi - 1].span != pt.span) off = a.noalloc ? 0 : slot_of(pt.span) * cap;
+        if (pi == 0 || parts[pi - 1].span != pt.span) {
+            sbase = span_base(pt.span);
+            off = 0;
+        }
         Chunk ch;
         ch.span = pt.span;
         ch.desc_begin = static_cast<uint32_t>(sp.first);
@@ -566,6 +537,73 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         ch.run_end = static_cast<uint32_t>(runs.size());
         chunks.push_back(std::move(ch));
     }
+
+}
+
+int run_call(vc_cipher *ctx, const CallArgs &a) {
+    const bool encrypting = a.op == Op::Encrypt || a.op == Op::EncryptHashed;
+    const bool uses_chain = encrypting || a.op == Op::Decrypt || a.op == Op::DebugKeysched;
+    const bool keysched_scratch = encrypting || a.op == Op::Decrypt;
+    const bool two_pass = ctx->passes == 2 && a.op != Op::Hash && a.op != Op::DebugKeysched;
+    const bool uses_scratch = keysched_scratch || two_pass;
+    const int dec_kernel = (a.op == Op::Decrypt) || (a.op == Op::DebugConfuse && a.decrypt);
+    const uint32_t n = ctx->key.n;
+    const size_t count = a.count;
+
+    // ---- validation (nothing enqueued yet) ----
+    std::map<uint32_t, uint64_t> seq_next;
+    for (size_t f = 0; f < count; ++f) {
+        const vc_shape &s = a.shapes[f];
+        int rc = check_shape(ctx, s, dec_kernel, a.op != Op::DebugConfuse);
+        if (rc) return rc;
+        const uint64_t L = frame_bytes(s);
+        if (a.op != Op::DebugKeysched && a.op != Op::DebugKeygen && !a.in[f]) return VC_EINVAL;
+        if ((encrypting || a.op == Op::Decrypt || a.op == Op::DebugConfuse) && !a.out[f]) return VC_EINVAL;
+        if ((encrypting || a.op == Op::DebugConfuse || a.op == Op::Decrypt) && overlaps(a.in[f], L, a.out[f], L))
+            return VC_EINVAL;
+        if (a.op == Op::DebugConfuse && (!a.dbgD[f] || !a.dbgB[f])) return VC_EINVAL;
+        if ((a.op == Op::DebugKeysched || a.op == Op::DebugKeygen) && (!a.kIR[f] || !a.kD[f] || !a.kB[f]))
+            return VC_EINVAL;
+        if (uses_scratch && scratch_need(s, n, keysched_scratch, two_pass) > (a.noalloc ? kNoAllocData : slot_bytes(ctx)))
+            return VC_ENOMEM;
+        if (uses_chain) {
+            if (s.stream >= ctx->max_streams) return VC_EINVAL;
+            auto it = seq_next.find(s.stream);
+            const uint64_t expect = (it == seq_next.end()) ? ctx->next_seq[s.stream] : it->second;
+            if (s.seq != expect) return VC_EORDER;
+            seq_next[s.stream] = expect + 1;
+        }
+    }
+    // descriptors of a no-alloc call: frame descriptors, at most one stream
+    // run and one chain record per frame, each table 256-byte aligned
+    if (a.noalloc && align_up(sizeof(FrameDesc) * count, 256) + align_up(sizeof(StreamRun) * count, 256) +
+                             align_up(sizeof(ChainRec) * count, 256) > kNoAllocDesc)
+        return VC_EINVAL;
+    if (count == 0) return VC_OK;
+    if ((uses_chain || uses_scratch) && !a.noalloc) {
+        const hipError_t e = ensure_streams(ctx);
+        if (e != hipSuccess) return map_err(e);
+    }
+
+    // ---- plan spans (consecutive frames whose scratch fits a slot) and parts ----
+    const bool overlap = (encrypting || a.op == Op::Decrypt) && ctx->parts > 1 && !a.noalloc;
+    const size_t cap = a.noalloc ? kNoAllocData : slot_bytes(ctx);
+    Plan P;
+    // span j of a call uses scratch slot (slot_next + j) mod nslots; a no-alloc
+    // call reuses the data area of `scratch` for every span (one stream)
+    build_plan(ctx, a, keysched_scratch, two_pass, uses_chain, uses_scratch, dec_kernel, cap,
+               overlap ? ctx->parts : 1,
+               [&](uint32_t span) {
+                   return a.noalloc ? ctx->na_base + kNoAllocDesc
+                                    : ctx->d_scratch + ((ctx->slot_next + span) % ctx->nslots) * cap;
+               },
+               P);
+    const std::vector<FrameDesc> &desc = P.desc;
+    const std::vector<StreamRun> &runs = P.runs;
+    const std::vector<ChainRec> &order = P.order;
+    const std::vector<Chunk> &chunks = P.chunks;
+    const uint32_t nspans = P.nspans;
+    auto slot_of = [&](uint32_t span) { return (ctx->slot_next + span) % ctx->nslots; };
 
     // ---- stage and upload ----
     const size_t desc_bytes = align_up(sizeof(FrameDesc) * count, 256);
@@ -1221,7 +1259,7 @@ int vc_autotune(vc_cipher *ctx, int decrypt, uint32_t w, uint32_t h, uint32_t fr
         for (uint32_t f = 0; f < frames && e == hipSuccess; ++f) {
             uint8_t *base = buf + f * (4 * Lp + Dp);
             desc[f] = FrameDesc{base, base + Lp, nullptr, nullptr, reinterpret_cast<uint16_t *>(base + 4 * Lp),
-                                base + 2 * Lp, base + 3 * Lp, w, h, L};
+                                base + 2 * Lp, base + 3 * Lp, w, h, L, 0, 0};
             e = hipMemcpyAsync(base + 4 * Lp, D.data(), 2 * ND, hipMemcpyHostToDevice, st);
         }
         if (e == hipSuccess) e = hipMemsetAsync(buf, 0x5A, frames * (4 * Lp), st);
@@ -1289,6 +1327,154 @@ int vc_autotune(vc_cipher *ctx, int decrypt, uint32_t w, uint32_t h, uint32_t fr
     if (strip_out) *strip_out = best_strip;
     if (threads_out) *threads_out = best_threads;
     return VC_OK;
+}
+
+}  // extern "C"
+
+// ---- prepared batches ----
+
+struct vc_batch {
+    vc_cipher *ctx = nullptr;
+    int decrypt = 0;
+    bool two_pass = true;
+    uint32_t count = 0;
+    uint8_t *d_mem = nullptr;  // descriptors, then the batch's scratch
+    const FrameDesc *d_desc = nullptr;
+    const StreamRun *d_runs = nullptr;
+    const ChainRec *d_order = nullptr;
+    std::vector<Chunk> chunks;
+    std::vector<std::vector<ConfuseTuning>> tiling;  // per chunk, per shape group
+    std::map<uint32_t, uint64_t> frames_per_stream;
+};
+
+namespace {
+
+void batch_free(vc_batch *b) {
+    if (b->d_mem) (void)hipFree(b->d_mem);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vc_batch_prepare(vc_cipher *ctx, int decrypt, size_t count, const uint8_t *const *frames, const vc_shape *shapes,
+                     uint8_t *hashes, uint8_t *const *out, vc_batch **batch) {
+    if (batch) *batch = nullptr;
+    if (!ctx || !batch || count == 0 || count > 0xFFFFFFFFull || !frames || !shapes || !hashes || !out)
+        return VC_EINVAL;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return VC_EDEVICE;
+    const int dec = decrypt ? 1 : 0;
+    const bool two_pass = ctx->passes == 2;
+    const uint32_t n = ctx->key.n;
+    std::map<uint32_t, uint64_t> last_seq;
+    uint64_t need = 0;
+    for (size_t f = 0; f < count; ++f) {
+        const vc_shape &s = shapes[f];
+        const int rc = check_shape(ctx, s, dec, true);
+        if (rc) return rc;
+        const uint64_t L = frame_bytes(s);
+        if (!frames[f] || !out[f] || overlaps(frames[f], L, out[f], L)) return VC_EINVAL;
+        if (s.stream >= ctx->max_streams) return VC_EINVAL;
+        auto it = last_seq.find(s.stream);
+        if (it != last_seq.end() && s.seq <= it->second) return VC_EORDER;
+        last_seq[s.stream] = s.seq;
+        need += scratch_need(s, n, true, two_pass);
+    }
+    vc_batch *b = new (std::nothrow) vc_batch();
+    if (!b) return VC_ENOMEM;
+    b->ctx = ctx;
+    b->decrypt = dec;
+    b->two_pass = two_pass;
+    b->count = static_cast<uint32_t>(count);
+    for (size_t f = 0; f < count; ++f) b->frames_per_stream[shapes[f].stream] += 1;
+    CallArgs a{};
+    a.op = dec ? Op::Decrypt : Op::Encrypt;
+    a.count = count;
+    a.in = frames;
+    a.shapes = shapes;
+    if (dec) a.hashes = hashes;
+    else a.hashes_out = hashes;
+    a.out = out;
+    // descriptors first (at most one run and one chain record per frame),
+    // then one span of scratch for every frame
+    const size_t desc_max = align_up(sizeof(FrameDesc) * count, 256) + align_up(sizeof(StreamRun) * count, 256) +
+                            align_up(sizeof(ChainRec) * count, 256);
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(&b->d_mem), desc_max + need);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return map_err(e);
+    }
+    Plan P;
+    build_plan(ctx, a, true, two_pass, true, true, dec, need, 1, [&](uint32_t) { return b->d_mem + desc_max; }, P);
+    const size_t desc_bytes = align_up(sizeof(FrameDesc) * count, 256);
+    const size_t runs_bytes = align_up(sizeof(StreamRun) * count, 256);
+    e = hipMemcpy(b->d_mem, P.desc.data(), sizeof(FrameDesc) * count, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_mem + desc_bytes, P.runs.data(), sizeof(StreamRun) * P.runs.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(b->d_mem + desc_bytes + runs_bytes, P.order.data(), sizeof(ChainRec) * P.order.size(),
+                      hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return map_err(e);
+    }
+    b->d_desc = reinterpret_cast<const FrameDesc *>(b->d_mem);
+    b->d_runs = reinterpret_cast<const StreamRun *>(b->d_mem + desc_bytes);
+    b->d_order = reinterpret_cast<const ChainRec *>(b->d_mem + desc_bytes + runs_bytes);
+    b->chunks = P.chunks;
+    for (const Chunk &ch : b->chunks) {
+        std::vector<ConfuseTuning> t;
+        for (const Group &gr : ch.groups) t.push_back(choose_tiling(ctx, dec, gr.w, gr.h));
+        b->tiling.push_back(std::move(t));
+    }
+    *batch = b;
+    return VC_OK;
+}
+
+int vc_batch_launch(vc_batch *b, void *stream) {
+    if (!b) return VC_EINVAL;
+    vc_cipher *ctx = b->ctx;
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return VC_EDEVICE;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const uint32_t n = ctx->key.n;
+    hipError_t e = hipSuccess;
+    if (!b->decrypt) e = launch_sha256_subframes(b->d_desc, b->count, n, s);
+    const hipStream_t ws = s;
+    for (size_t ci = 0; ci < b->chunks.size() && e == hipSuccess; ++ci) {
+        const Chunk &ch = b->chunks[ci];
+        e = launch_lhcs_chain(b->d_runs + ch.run_begin, b->d_order, ch.run_end - ch.run_begin, ctx->d_state, n,
+                              ctx->key.gamma, ctx->d_flags, s);
+        if (e == hipSuccess)
+            e = launch_lhcs_keygen(b->d_desc + ch.desc_begin, ch.desc_end - ch.desc_begin, n, ctx->key.gamma,
+                                   ctx->d_flags, ws);
+        for (size_t gi = 0; gi < ch.groups.size() && e == hipSuccess; ++gi) {
+            const Group &gr = ch.groups[gi];
+            const ConfuseTuning &t = b->tiling[ci][gi];
+            if (!b->two_pass) {
+                e = launch_confuse(b->decrypt, b->d_desc, gr.first, gr.count, gr.w, gr.h, gr.align >= 1, t, ws);
+            } else {
+                for (int pass = 0; pass < 2 && e == hipSuccess; ++pass)
+                    e = launch_shift(b->decrypt, pass, b->d_desc, gr.first, gr.count, gr.w, gr.h, gr.align, t,
+                                     ctx->lds_limit, ws);
+            }
+        }
+    }
+    if (e != hipSuccess) return map_err(e);
+    for (const auto &kv : b->frames_per_stream) ctx->next_seq[kv.first] += kv.second;
+    ctx->last_stream = s;
+    return VC_OK;
+}
+
+void vc_batch_destroy(vc_batch *b) {
+    if (!b) return;
+    DeviceGuard g(b->ctx->device);
+    (void)hipDeviceSynchronize();
+    batch_free(b);
 }
 
 }  // extern "C"
@@ -1424,6 +1610,14 @@ int vc_frame_diff(size_t count, const uint8_t *const *a, const uint8_t *const *b
                               reinterpret_cast<unsigned long long *>(out), s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return map_err(e);
+}
+
+int vc_bandwidth_probe(int kind, const uint8_t *a, const uint8_t *b, uint8_t *out, size_t bytes, void *stream) {
+    if ((kind != 0 && kind != 1) || !a || !out || (kind == 1 && !b) || bytes % 16) return VC_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(out) |
+         (kind == 1 ? reinterpret_cast<uintptr_t>(b) : 0)) & 15)
+        return VC_EINVAL;
+    return map_err(launch_stream_probe(kind, a, b, out, bytes, static_cast<hipStream_t>(stream)));
 }
 
 uint32_t vc_max_frame_height(const vc_cipher *ctx) {

@@ -157,6 +157,10 @@ hipError_t launch_pair_moments(const StatFrame *d_frames, uint32_t count, uint64
                                const uint32_t *d_positions, unsigned long long *d_moments, hipStream_t s);
 hipError_t launch_frame_diff(const StatFrame *d_a, const StatFrame *d_b, uint32_t count, uint64_t max_bytes,
                              unsigned long long *d_out, hipStream_t s);
+// out = a (kind 0) or a ^ b (kind 1) over `bytes` (a multiple of 16,
+// 16-byte aligned pointers), one 16-byte word per thread.
+hipError_t launch_stream_probe(int kind, const uint8_t *a, const uint8_t *b, uint8_t *out, uint64_t bytes,
+                               hipStream_t s);
 
 // A wave of SHA-256 compression or of the key-stream integrator issues an
 // instruction almost every cycle, so two such waves on one SIMD each run at

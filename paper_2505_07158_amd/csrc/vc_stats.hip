@@ -189,7 +189,36 @@ __global__ __launch_bounds__(kHistThreads) void frame_diff(const StatFrame *__re
     if (threadIdx.x < 12 && acc[threadIdx.x]) atomicAdd(&out[12ull * f + threadIdx.x], acc[threadIdx.x]);
 }
 
+// Streaming reference for the HBM ceiling of the confusion kernels: one
+// 16-byte word per thread, out = a (KIND 0) or out = a ^ b (KIND 1).
+typedef uint32_t u32x4_s __attribute__((ext_vector_type(4)));
+template <int KIND>
+__global__ __launch_bounds__(256) void stream_probe(const u32x4_s *__restrict__ a, const u32x4_s *__restrict__ b,
+                                                    u32x4_s *__restrict__ out, uint64_t n16) {
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (i >= n16) return;
+    const VC_GLOBAL u32x4_s *ga = gmem(a);
+    VC_GLOBAL u32x4_s *go = gmem(out);
+    if (KIND == 0) go[i] = ga[i];
+    else go[i] = ga[i] ^ gmem(b)[i];
+}
+
 }  // namespace
+
+hipError_t launch_stream_probe(int kind, const uint8_t *a, const uint8_t *b, uint8_t *out, uint64_t bytes,
+                               hipStream_t s) {
+    const uint64_t n16 = bytes / 16, groups = (n16 + 255) / 256;
+    if (groups == 0) return hipSuccess;
+    if (groups > 0x7FFFFFFFull) return hipErrorInvalidValue;
+    const auto *a4 = reinterpret_cast<const u32x4_s *>(a);
+    const auto *b4 = reinterpret_cast<const u32x4_s *>(b);
+    auto *o4 = reinterpret_cast<u32x4_s *>(out);
+    if (kind == 0)
+        hipLaunchKernelGGL(stream_probe<0>, dim3(static_cast<uint32_t>(groups)), dim3(256), 0, s, a4, b4, o4, n16);
+    else
+        hipLaunchKernelGGL(stream_probe<1>, dim3(static_cast<uint32_t>(groups)), dim3(256), 0, s, a4, b4, o4, n16);
+    return hipGetLastError();
+}
 
 hipError_t launch_frame_diff(const StatFrame *d_a, const StatFrame *d_b, uint32_t count, uint64_t max_bytes,
                              unsigned long long *d_out, hipStream_t s) {

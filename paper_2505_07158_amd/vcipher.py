@@ -77,6 +77,15 @@ def _load() -> C.CDLL:
     L.vc_frame_diff.argtypes = [C.c_size_t, C.POINTER(vp), C.POINTER(vp), C.POINTER(VcShape), vp, vp]
     L.vc_autotune.argtypes = [vp, C.c_int, C.c_uint32, C.c_uint32, C.c_uint32, C.POINTER(C.c_uint32),
                               C.POINTER(C.c_uint32)]
+    L.vc_batch_prepare.argtypes = [vp, C.c_int, C.c_size_t, C.POINTER(vp), C.POINTER(VcShape), u8p, C.POINTER(vp),
+                                   C.POINTER(vp)]
+    L.vc_batch_prepare.restype = C.c_int
+    L.vc_batch_launch.argtypes = [vp, vp]
+    L.vc_batch_launch.restype = C.c_int
+    L.vc_batch_destroy.argtypes = [vp]
+    L.vc_batch_destroy.restype = None
+    L.vc_bandwidth_probe.argtypes = [C.c_int, vp, vp, vp, C.c_size_t, vp]
+    L.vc_bandwidth_probe.restype = C.c_int
     L.vc_max_frame_height.argtypes = [vp]
     L.vc_max_frame_height.restype = C.c_uint32
     L.vc_scratch_per_frame.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
@@ -261,6 +270,51 @@ def vc_debug_keysched(ctx: int, shapes_hw: Sequence[Tuple[int, int]], streams: S
     rc = lib.vc_debug_keysched(C.c_void_p(ctx), len(shapes_hw), arr, C.c_void_p(hashes.data_ptr()),
                                _ptrs(IR), _ptrs(D), _ptrs(B), C.c_void_p(_stream_handle(stream)))
     _check(rc, "vc_debug_keysched")
+
+
+class Batch:
+    """A prepared batch (vc_batch_prepare): launch() only enqueues kernels, so
+    it can be captured in a torch.cuda.CUDAGraph (a HIP graph) and replayed.
+    The tensors given here must stay alive as long as the batch."""
+
+    def __init__(self, ctx: int, decrypt: bool, frames: Sequence[torch.Tensor], streams: Sequence[int],
+                 seqs: Sequence[int], hashes: torch.Tensor, out: Sequence[torch.Tensor]):
+        for t in list(frames) + list(out):
+            _check_frame(t)
+        if hashes.dtype != torch.uint8 or not hashes.is_cuda or hashes.numel() < 32 * len(frames):
+            raise ValueError("hashes must be a CUDA uint8 tensor of count*32 bytes")
+        self._keep = (list(frames), hashes, list(out))
+        h = C.c_void_p()
+        _check(lib.vc_batch_prepare(C.c_void_p(ctx), 1 if decrypt else 0, len(frames), _ptrs(frames),
+                                    _shapes(frames, streams, seqs), C.c_void_p(hashes.data_ptr()), _ptrs(out),
+                                    C.byref(h)), "vc_batch_prepare")
+        self.handle = h.value
+
+    def launch(self, stream: Optional[torch.cuda.Stream] = None) -> None:
+        _check(lib.vc_batch_launch(C.c_void_p(self.handle), C.c_void_p(_stream_handle(stream))), "vc_batch_launch")
+
+    def close(self) -> None:
+        if self.handle:
+            lib.vc_batch_destroy(C.c_void_p(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def vc_bandwidth_probe(kind: int, a: torch.Tensor, b: Optional[torch.Tensor], out: torch.Tensor,
+                       stream: Optional[torch.cuda.Stream] = None) -> None:
+    """Streaming reference (not the cipher): out = a (kind 0) or a ^ b (kind 1), all uint8 CUDA tensors."""
+    nbytes = out.numel()
+    for t in (a, b, out):
+        if t is not None and (not t.is_cuda or t.dtype != torch.uint8 or not t.is_contiguous() or t.numel() < nbytes):
+            raise ValueError("contiguous CUDA uint8 tensors of at least out.numel() bytes expected")
+    _check(lib.vc_bandwidth_probe(kind, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr() if b is not None else 0),
+                                  C.c_void_p(out.data_ptr()), nbytes, C.c_void_p(_stream_handle(stream))),
+           "vc_bandwidth_probe")
 
 
 def vc_debug_keygen(ctx: int, shapes_hw: Sequence[Tuple[int, int]], IR: Sequence[torch.Tensor],

@@ -1,12 +1,14 @@
 """The continuous-batching loop on the GPU: each stream's result is the same
 alone and in the mix (mixed resolutions, encrypt and decrypt requests,
-out-of-order arrivals, batches of several streams in flight at once)."""
+out-of-order arrivals, batches of several streams in flight at once), and
+every served frame equals the oracle's encryption or the plaintext."""
 import random
 
 import numpy as np
 import pytest
 import torch
 
+import oracle
 from gpu_util import require_gpu, to_dev, to_np
 from workload.synth import SynthVideo, key_bytes
 
@@ -71,11 +73,22 @@ def test_results_alone_equal_results_in_the_mix(per_class, hash_first):
     assert len(sched.completed) == len(reqs)
     assert any(k == "enc" and size > 1 for k, size in sched.batches), sched.batches
     assert any(k == "hash" for k, _ in sched.batches) == hash_first
+    base = oracle.key_from_bytes(kb)
+    ref = {}
+    for (kind, s), v in vids.items():
+        Cs, Hs, _ = oracle.encrypt_stream(base, gamma, n, list(v))
+        ref[(kind, s)] = (Cs, Hs)
+    for s in range(len(dec_shapes)):          # the sender's ciphertext is the oracle's
+        Cs, Hs = ref[("dec", s)]
+        for t in range(T):
+            assert np.array_equal(to_np(dec_in[s][0][t]), Cs[t]) and to_np(dec_in[s][1][t]).tobytes() == Hs[t]
     for r in reqs:
         if r.kind == "enc":
             C, H = alone[r.stream]
+            Cs, Hs = ref[("enc", r.stream)]
             assert np.array_equal(to_np(r.out), C[r.seq]), (r.stream, r.seq)
-            assert to_np(r.hashes).tobytes() == H[r.seq].tobytes()
+            assert np.array_equal(to_np(r.out), Cs[r.seq]), (r.stream, r.seq)
+            assert to_np(r.hashes).tobytes() == H[r.seq].tobytes() == Hs[r.seq]
         else:
             assert np.array_equal(to_np(r.out), vids[("dec", r.stream)][r.seq]), (r.stream, r.seq)
     assert be.status_ok()
