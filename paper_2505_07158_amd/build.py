@@ -4,8 +4,10 @@
 
 Every source under csrc/ is compiled by hipcc for gfx950 with FP contraction
 disabled (the key schedule must round exactly like any IEEE-754 FP64
-implementation) and packed-FP32 instruction selection disabled, then linked
-into paper_2505_07158_amd/libvcipher.so.
+implementation) and packed-FP32 instruction selection disabled (the
+target feature applies to the device pass; the host pass warns that it does
+not know it -- tests/test_build_flags.py checks the device assembly), then
+linked into paper_2505_07158_amd/libvcipher.so.
 """
 from __future__ import annotations
 
