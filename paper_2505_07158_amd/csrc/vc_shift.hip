@@ -62,6 +62,22 @@ __device__ __forceinline__ void map_strip(uint32_t g, uint32_t nstrips, int xcd_
 constexpr uint32_t kRowThreads = 256;
 constexpr uint32_t kRowsPerGroup = 4;
 constexpr uint32_t kRowShiftTable = 16 * kRowsPerGroup;  // LDS bytes of the rows' shift amounts
+constexpr uint32_t kStageLoads = 6;  // staging loads in flight per thread (4 1080p rows: 5.6 per thread)
+
+// Copies n16 16-byte words into LDS, kStageLoads loads in flight per
+// thread: src(k) is the global address of word k, dst(k) its LDS address.
+template <typename Src, typename Dst>
+__device__ __forceinline__ void stage16(uint32_t n16, Src src, Dst dst) {
+    for (uint32_t k0 = threadIdx.x; k0 < n16; k0 += kStageLoads * kRowThreads) {
+        u32x4 v[kStageLoads];
+#pragma unroll
+        for (uint32_t u = 0; u < kStageLoads; ++u)
+            if (k0 + u * kRowThreads < n16) v[u] = *src(k0 + u * kRowThreads);
+#pragma unroll
+        for (uint32_t u = 0; u < kStageLoads; ++u)
+            if (k0 + u * kRowThreads < n16) *dst(k0 + u * kRowThreads) = v[u];
+    }
+}
 
 // Four output bytes (pixels 4m..4m+3) of one channel: bits s..s+31 of the
 // channel's bit row, from source pixels q..q+4 (mod w).  `row` is the source
@@ -162,27 +178,33 @@ __global__ __launch_bounds__(kRowThreads) void row_shift(const FrameDesc *__rest
             // contiguous run of 16-byte words, read in memory order (every
             // strip but the last has nr * SB / 16 of them)
             const uint32_t ns = (rb + xs - 1) >> sl, cps = nr * (xs / 16), n16 = nr * (rb / 16);
-            for (uint32_t k = threadIdx.x; k < n16; k += kRowThreads) {
-                uint32_t st = k / cps;
-                if (st > ns - 1) st = ns - 1;
-                const uint32_t k0 = st << sl, sbw = (rb - k0 < xs) ? rb - k0 : xs;
-                const uint32_t within = k - st * cps, q16 = sbw / 16;
-                const uint32_t rr = within / q16, e = within - rr * q16;
-                *reinterpret_cast<u32x4 *>(rowbuf + rr * lds_row + k0 + 16 * e) =
-                    *reinterpret_cast<const VC_GLOBAL u32x4 *>(src + static_cast<uint64_t>(k0) * h +
-                                                               static_cast<uint64_t>(r0) * sbw + 16 * within);
-            }
+            // word k: strip st, position `within` of the strip's run of nr rows
+            auto strip_of = [&](uint32_t k) { return k / cps < ns - 1 ? k / cps : ns - 1; };
+            stage16(
+                n16,
+                [&](uint32_t k) {
+                    const uint32_t st = strip_of(k), k0 = st << sl, sbw = (rb - k0 < xs) ? rb - k0 : xs;
+                    return reinterpret_cast<const VC_GLOBAL u32x4 *>(
+                        src + static_cast<uint64_t>(k0) * h + static_cast<uint64_t>(r0) * sbw + 16 * (k - st * cps));
+                },
+                [&](uint32_t k) {
+                    const uint32_t st = strip_of(k), k0 = st << sl, sbw = (rb - k0 < xs) ? rb - k0 : xs;
+                    const uint32_t within = k - st * cps, q16 = sbw / 16;
+                    const uint32_t rr = within / q16, e = within - rr * q16;
+                    return reinterpret_cast<u32x4 *>(rowbuf + rr * lds_row + k0 + 16 * e);
+                });
         } else {
             const VC_GLOBAL uint8_t *s0 = src + static_cast<uint64_t>(r0) * rb;
             const bool v16 = aligned && (rb % 16 == 0) && ((reinterpret_cast<uintptr_t>(src) & 15) == 0);
             if (v16) {
                 // the rows are contiguous: nr * rb / 16 uint4, row k at LDS offset k * lds_row
                 const uint32_t per = rb / 16, n16 = nr * per;
-                for (uint32_t k = threadIdx.x; k < n16; k += kRowThreads) {
-                    const uint32_t rr = k / per, e = k - rr * per;
-                    reinterpret_cast<u32x4 *>(rowbuf + rr * lds_row)[e] =
-                        reinterpret_cast<const VC_GLOBAL u32x4 *>(s0)[k];
-                }
+                stage16(
+                    n16, [&](uint32_t k) { return reinterpret_cast<const VC_GLOBAL u32x4 *>(s0) + k; },
+                    [&](uint32_t k) {
+                        const uint32_t rr = k / per, e = k - rr * per;
+                        return reinterpret_cast<u32x4 *>(rowbuf + rr * lds_row) + e;
+                    });
             } else if (aligned) {
                 const uint32_t per = rb / 4, n4 = nr * per;
                 for (uint32_t k = threadIdx.x; k < n4; k += kRowThreads) {
