@@ -544,7 +544,8 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
     const bool encrypting = a.op == Op::Encrypt || a.op == Op::EncryptHashed;
     const bool uses_chain = encrypting || a.op == Op::Decrypt || a.op == Op::DebugKeysched;
     const bool keysched_scratch = encrypting || a.op == Op::Decrypt;
-    const bool two_pass = ctx->passes == 2 && a.op != Op::Hash && a.op != Op::DebugKeysched;
+    const bool two_pass =
+        ctx->passes == 2 && a.op != Op::Hash && a.op != Op::DebugKeysched && a.op != Op::DebugKeygen;
     const bool uses_scratch = keysched_scratch || two_pass;
     const int dec_kernel = (a.op == Op::Decrypt) || (a.op == Op::DebugConfuse && a.decrypt);
     const uint32_t n = ctx->key.n;

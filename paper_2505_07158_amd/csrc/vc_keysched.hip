@@ -255,24 +255,15 @@ __global__ __launch_bounds__(128) void lhcs_keygen(const FrameDesc *__restrict__
             const VC_GLOBAL double *Q = A + 4;
             l = odd ? V4{Q[0], A[1], Q[2], A[3]} : V4{A[0], Q[1], A[2], Q[3]};
         }
-        // Finiteness of this LHCS after its worker's last step (a non-finite
-        // value never becomes finite again under +, -, x, so the last state
-        // decides); the lanes keep integrating past it up to the wave's
-        // longest worker.
-        bool ok = true;
-        const uint64_t last_blk = steps ? (steps - 1) / kKgHalf : ~0ull;
-        const uint32_t last_j = steps ? static_cast<uint32_t>((steps - 1) % kKgHalf) : 0;
         for (uint32_t blk = 0; blk < nblk; ++blk) {
             V4 *slot = &ring[(blk & 1) * kKgHalf][lane];
 #pragma unroll
             for (uint32_t j = 0; j < kKgHalf; ++j) {
                 rk4_step(l, gamma);
                 slot[64 * j] = l;
-                if (blk == last_blk && j == last_j) ok = finite4(l);
             }
             __syncthreads();
         }
-        if (live && !ok) flags[0] = FLAG_NONFINITE;
         return;
     }
 
@@ -287,6 +278,10 @@ __global__ __launch_bounds__(128) void lhcs_keygen(const FrameDesc *__restrict__
     const uint64_t fast_hi = (s_a < s_b) ? s_b : steps;
     const uint32_t shr = 8 * (4 - phi);  // 32 when phi == 0
     const uint32_t jlo = odd ? 12 : 0;
+    // Finiteness of the worker's two LHCSs after its last step, read from the
+    // ring by this wave on either store path (a non-finite value never
+    // becomes finite again under +, -, x, so the last state decides).
+    bool ok = true;
     uint32_t carry = 0;  // word 5 of the previous step
 
     // Steps [fast_lo, fast_core) need no bytewise work at all; the last fast
@@ -305,6 +300,7 @@ __global__ __launch_bounds__(128) void lhcs_keygen(const FrameDesc *__restrict__
             for (uint32_t j = 0; j < kKgHalf; ++j) {
                 const V4 a = half[64 * j + (lane & ~1u)];
                 const V4 b = half[64 * j + (lane | 1u)];
+                if (s0 + j + 1 == steps) ok = finite4(a) && finite4(b);
                 const uint64_t u0 = bits(a.x) ^ bits(b.x), u1 = bits(a.y) ^ bits(b.y);
                 const uint64_t u2 = bits(a.z) ^ bits(b.z), u3 = bits(a.w) ^ bits(b.w);
                 const uint32_t w0 = static_cast<uint32_t>(u0);
@@ -367,8 +363,10 @@ __global__ __launch_bounds__(128) void lhcs_keygen(const FrameDesc *__restrict__
                 }
             }
             carry = w[5];
+            if (s + 1 == steps) ok = finite4(a) && finite4(b);
         }
     }
+    if (live && !ok) flags[0] = FLAG_NONFINITE;
 }
 
 }  // namespace

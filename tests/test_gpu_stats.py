@@ -170,3 +170,27 @@ def test_ciphertext_statistics_are_uniform():
     assert abs(enc["lse"] - S.LSE_IDEAL) < 0.002
     for d in S.DIRECTIONS:
         assert enc[f"corr_{d}"] < 0.03
+
+
+def test_bandwidth_probe_copies_and_xors():
+    """The streaming reference kernel (vc_bandwidth_probe): out = a and
+    out = a ^ b over a buffer that spans many workgroups and a ragged last
+    one; misaligned or non-multiple-of-16 sizes are rejected."""
+    dev = require_gpu()
+    from paper_2505_07158_amd import vcipher as V
+    g = torch.Generator(device=dev)
+    g.manual_seed(7)
+    n = 16 * (256 * 1000 + 37)
+    a = torch.randint(0, 256, (n,), dtype=torch.uint8, device=dev, generator=g)
+    b = torch.randint(0, 256, (n,), dtype=torch.uint8, device=dev, generator=g)
+    out = torch.zeros(n, dtype=torch.uint8, device=dev)
+    V.vc_bandwidth_probe(0, a, b, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, a)
+    V.vc_bandwidth_probe(1, a, b, out)
+    torch.cuda.synchronize()
+    assert torch.equal(out, a ^ b)
+    with pytest.raises(V.VcError):
+        V.vc_bandwidth_probe(1, a[1:], b[1:], out[:n - 16])      # misaligned
+    with pytest.raises(V.VcError):
+        V.vc_bandwidth_probe(0, a, b, out[:n - 8])               # not a multiple of 16 bytes
