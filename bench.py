@@ -54,15 +54,11 @@ def parse():
     ap.add_argument("--max-batch", type=int, default=256, help="serving: frames per batch at most")
     ap.add_argument("--plain-frames", type=int, default=400, help="serving: arrivals replayed one frame per launch")
     ap.add_argument("--inflight", type=int, default=1, help="serving: batches in flight per kind and resolution")
-    ap.add_argument("--inflight-4k", type=int, default=0,
-                    help="serving: batches in flight per kind at 3840x2160 (0 = --inflight)")
     ap.add_argument("--hash-first", type=int, default=0,
                     help="serving: 1 = hash each encrypt request on arrival, then chain/keystream/confusion in "
                     "stream order (encrypt_frames_hashed); 0 = one encrypt_frames call per batch")
     ap.add_argument("--serve-parts", type=int, default=1, help="serving: parts per call (vc_set_overlap)")
     ap.add_argument("--serve-side", type=int, default=0, help="serving: side streams per context (vc_set_overlap)")
-    ap.add_argument("--serve-side-1080p", type=int, default=0,
-                    help="serving: side streams of the 1920x1080 contexts (consecutive batches' keygen overlap)")
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--n", type=int, default=32, help="worker count (key material)")
@@ -184,16 +180,17 @@ def serving_run(args, duration: float, plain_frames: int) -> dict:
     3840x2160}; Poisson arrivals at each stream's frame rate for
     --duration seconds; 30 % of the streams are decrypt streams (their
     ciphertext and hashes come from a separate sender context with the same
-    key).  The continuous-batching loop (paper_2505_07158_amd.serving) runs
-    the trace, then the first --plain-frames arrivals run with one frame per
-    launch (the plain per-frame path).  Reports p50/p99 arrival-to-completion latency, per
-    resolution too, delivered frames/s and the delay rate (frames later than
-    one frame interval, 1000/FPS ms)."""
+    key).  The library's serving loop (vc_server_run_trace: continuous
+    batching, one sender and one receiver context per resolution) replays
+    the trace, then the first --plain-frames arrivals with one frame per
+    launch (the plain per-frame path).  Reports p50/p99 arrival-to-completion
+    latency, per resolution and frame rate too, delivered frames/s and the
+    delay rate (frames later than one frame interval, 1000/FPS ms)."""
     import numpy as np
     import torch
 
     from paper_2505_07158_amd import vcipher as V
-    from paper_2505_07158_amd.serving import GpuBackend, Request, Scheduler
+    from paper_2505_07158_amd.serving import Server
     from workload.synth import key_bytes
 
     dev = torch.device("cuda:0")
@@ -224,134 +221,100 @@ def serving_run(args, duration: float, plain_frames: int) -> dict:
         fr.random_(0, 256)
         pool.append(fr)
     budget = int(args.hbm_budget_gb * (1 << 30))
-
     R = 8   # output buffers per stream (frames of a stream in flight at most)
-
-    def make_backend(max_inflight, hash_first):
-        cls = (lambda r: (streams[r.stream]["w"], streams[r.stream]["h"]))
-        # one context pair per resolution, each with its chain stream and
-        # --serve-side side streams, and one device stream per in-flight batch
-        # of each (kind, resolution)
-        return cls, GpuBackend(kb, gamma, n, max_streams=S, scratch_bytes=max(budget // len(res_set), 1 << 30),
-                               overlap=lambda kind, c: (args.serve_parts, args.serve_side_1080p
-                                                        if c == (1920, 1080) else args.serve_side, 2),
-                               device_streams=lambda kind, c: max(max_inflight(kind, c), 1),
-                               classes=res_set, batch_class=cls, hash_first=hash_first)
-
     outs = [torch.empty((R,) + tuple(pool[s].shape[1:]), dtype=torch.uint8, device=dev) for s in range(S)]
     first = [torch.empty_like(pool[s]) for s in range(S)]   # decrypt outputs of seq < P, kept for the check
     hring = [torch.empty((R, 32), dtype=torch.uint8, device=dev) for _ in range(S)]
+    sender = V.Cipher.from_bytes(kb, gamma, n, max_streams=S, scratch_bytes=max(budget // 4, 1 << 30))
+    dec_src = {}
+    for s, st in enumerate(streams):
+        if st["kind"] == "dec":
+            dec_src[s] = sender.encrypt(pool[s], streams=[s] * P)
+    torch.cuda.synchronize()
+    sender.close()
+
+    def request(i, ta, s, seq):
+        if streams[s]["kind"] == "enc":
+            frame, hashes, out = pool[s][seq % P], hring[s][seq % R], outs[s][seq % R]
+        else:
+            frame, hashes = dec_src[s][0][seq % P], dec_src[s][1][seq % P]
+            out = first[s][seq] if seq < P else outs[s][seq % R]
+        return Server.request(i, streams[s]["kind"], s, seq, frame, out, hashes, arrival=ta)
 
     def one_run(trace, max_batch, max_inflight, hash_first):
-        cls, be = make_backend(max_inflight, hash_first)
-        # warm-up on the backend itself (every kernel variant, every device
-        # stream of each kind and resolution), then the chains back to the key
-        for s, st in enumerate(streams):
-            if all(streams[x]["w"] != st["w"] or streams[x]["h"] != st["h"] for x in range(s)):
-                for kind in (("hash", "enc", "dec") if hash_first else ("enc", "dec")):
-                    for q in range(max_inflight(kind, (st["w"], st["h"]))):
-                        f = pool[s][0]
-                        h32 = torch.zeros(32, dtype=torch.uint8, device=dev)
-                        r = Request(stream=s, seq=q, kind="enc" if kind == "hash" else kind, frame=f,
-                                    out=torch.empty_like(f), hashes=h32, hashed=hash_first)
-                        be.launch(kind, [r])
+        srv = Server(kb, gamma, n, res_set, max_streams=S, hbm_budget=budget, max_inflight=max_inflight,
+                     max_batch=max_batch, max_stream_inflight=R, hash_first=hash_first, parts=args.serve_parts,
+                     side_streams=args.serve_side, scratch_bytes=max(budget // len(res_set), 1 << 30))
+        # warm-up: two frames of every stream at once (every kernel variant on
+        # the device streams of each kind and resolution), then the chains
+        # back to the key
+        warm = [request(k, 0.0, s, seq) for k, (s, seq) in enumerate((s, q) for s in range(S) for q in range(2))]
+        srv.run_trace(warm)
         torch.cuda.synchronize()
-        be.reset_chains(range(S))
-        be.launch_seconds = 0.0
-        dec_src = {}
-        sender = V.Cipher.from_bytes(kb, gamma, n, max_streams=S, scratch_bytes=max(budget // 4, 1 << 30))
-        for s, st in enumerate(streams):
-            if st["kind"] == "dec":
-                C, H = sender.encrypt(pool[s], streams=[s] * P)
-                dec_src[s] = (C, H)
-        torch.cuda.synchronize()
-        sender.close()
-        sched = Scheduler(be.launch, hbm_budget=budget, max_inflight=max_inflight, max_batch=max_batch,
-                          batch_class=cls, max_stream_inflight=R, hash_first=hash_first)
-        reqs = []
-        i = 0
-        # no cyclic garbage collection while the trace runs (a full
-        # collection over the growing request list would pause the loop)
+        srv.reset()
+        before = srv.stats().batches_launched
+        reqs = [request(i, ta, s, seq) for i, (ta, s, seq) in enumerate(trace)]
         gc.collect()
-        gc.disable()
-        try:
-            t0 = time.perf_counter()
-            while i < len(trace) or not sched.idle():
-                now = time.perf_counter() - t0
-                while i < len(trace) and trace[i][0] <= now:
-                    ta, s, seq = trace[i]
-                    st = streams[s]
-                    if st["kind"] == "enc":
-                        frame, hashes, out = pool[s][seq % P], hring[s][seq % R], outs[s][seq % R]
-                    else:
-                        frame, hashes = dec_src[s][0][seq % P], dec_src[s][1][seq % P]
-                        out = first[s][seq] if seq < P else outs[s][seq % R]
-                    r = Request(stream=s, seq=seq, kind=st["kind"], frame=frame, out=out,
-                                hashes=hashes, nbytes=be.footprint(st["w"], st["h"]), arrival=t0 + ta)
-                    reqs.append(r)
-                    sched.submit(r)
-                    i += 1
-                if not sched.pump():
-                    time.sleep(0.0001)
-            torch.cuda.synchronize()
-            wall = time.perf_counter() - t0
-        finally:
-            gc.enable()
+        cpu0 = time.process_time()
+        t0 = time.perf_counter()
+        done = srv.run_trace(reqs)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        cpu = time.process_time() - cpu0
+        batches = int(srv.stats().batches_launched - before)
+        status_ok = srv.status() == 0
+        srv.close()
         # decrypt requests whose ciphertext matches their sequence number
-        ok = all(torch.equal(first[r.stream][r.seq], pool[r.stream][r.seq]) for r in reqs
-                 if r.kind == "dec" and r.seq < P)
-        status_ok = be.status_ok()
-        host_launch_s = be.launch_seconds
-        be.close()
-        lat = np.array([1000.0 * r.latency for r in reqs])
-        wait = np.array([1000.0 * (r.launched - r.arrival) for r in reqs])     # queued on the host
-        serv = np.array([1000.0 * (r.done - r.launched) for r in reqs])        # first launch to completion
-        late = np.array([1000.0 * r.latency > 1000.0 / streams[r.stream]["fps"] for r in reqs])
+        ok = all(torch.equal(first[s][seq], pool[s][seq]) for _, s, seq in trace
+                 if streams[s]["kind"] == "dec" and seq < P)
+        arrival = np.array([ta for ta, _, _ in trace])
+        launched = np.array([done[i].launched for i in range(len(trace))])
+        fin = np.array([done[i].done for i in range(len(trace))])
+        hashed = sum(int(done[i].hashed) for i in range(len(trace)))
+        lat = 1000.0 * (fin - arrival)
+        wait = 1000.0 * (launched - arrival)     # queued on the host
+        serv = 1000.0 * (fin - launched)         # first launch to completion
+        fps_of = np.array([streams[s]["fps"] for _, s, _ in trace])
+        late = lat > 1000.0 / fps_of
+
+        def summary(sel, extra=False):
+            d = {"frames": int(len(sel)), "p50_ms": round(pct(lat[sel], 50), 3), "p99_ms": round(pct(lat[sel], 99), 3),
+                 "delay_rate": round(float(late[sel].mean()), 4)}
+            if extra:
+                d["wait_p50_p99_ms"] = [round(pct(wait[sel], q), 3) for q in (50, 99)]
+                d["service_p50_p99_ms"] = [round(pct(serv[sel], q), 3) for q in (50, 99)]
+            return d
+
         # delay rate (frames later than one frame interval, Sec. V) per FPS
-        # class and per stream
-        per_fps = {}
-        for fps in fps_set:
-            sel = [k for k, r in enumerate(reqs) if streams[r.stream]["fps"] == fps]
-            if sel:
-                per_fps[str(fps)] = {"frames": len(sel), "p50_ms": round(float(np.percentile(lat[sel], 50)), 3),
-                                     "p99_ms": round(float(np.percentile(lat[sel], 99)), 3),
-                                     "delay_rate": round(float(late[sel].mean()), 4)}
-        by_stream = {}
-        for k, r in enumerate(reqs):
-            by_stream.setdefault(r.stream, []).append(k)
-        per_stream = [[s_, streams[s_]["fps"], f"{streams[s_]['w']}x{streams[s_]['h']}", streams[s_]["kind"],
-                       len(ks), round(float(late[ks].mean()), 4)] for s_, ks in sorted(by_stream.items())]
+        # class, per resolution and per stream
+        per_fps = {str(f): summary(np.flatnonzero(fps_of == f)) for f in fps_set if (fps_of == f).any()}
+        res_of = [(streams[s]["w"], streams[s]["h"]) for _, s, _ in trace]
         per_res = {}
-        for (w, h) in res_set:
-            sel = [k for k, r in enumerate(reqs) if (streams[r.stream]["w"], streams[r.stream]["h"]) == (w, h)]
-            if sel:
-                per_res[f"{w}x{h}"] = {"frames": len(sel), "p50_ms": round(float(np.percentile(lat[sel], 50)), 3),
-                                       "p99_ms": round(float(np.percentile(lat[sel], 99)), 3),
-                                       "delay_rate": round(float(late[sel].mean()), 4),
-                                       "wait_p50_p99_ms": [round(float(np.percentile(wait[sel], q)), 3)
-                                                           for q in (50, 99)],
-                                       "service_p50_p99_ms": [round(float(np.percentile(serv[sel], q)), 3)
-                                                              for q in (50, 99)]}
-        sizes = [b for _, b in sched.batches]
-        return {"frames": len(reqs), "wall_s": round(wall, 3), "frames_per_s": round(len(reqs) / wall, 1),
-                "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+        for wh in res_set:
+            sel = np.array([k for k, r in enumerate(res_of) if r == wh], dtype=int)
+            if len(sel):
+                per_res[f"{wh[0]}x{wh[1]}"] = summary(sel, extra=True)
+        sid = np.array([s for _, s, _ in trace])
+        per_stream = []
+        for s_ in sorted(set(sid.tolist())):
+            ks = np.flatnonzero(sid == s_)
+            per_stream.append([s_, streams[s_]["fps"], f"{streams[s_]['w']}x{streams[s_]['h']}", streams[s_]["kind"],
+                               int(len(ks)), round(float(late[ks].mean()), 4)])
+        return {"frames": len(trace), "wall_s": round(wall, 3), "frames_per_s": round(len(trace) / wall, 1),
+                "p50_ms": round(pct(lat, 50), 3), "p99_ms": round(pct(lat, 99), 3),
                 "delay_rate": round(float(late.mean()), 4), "per_resolution": per_res, "per_fps": per_fps,
                 "per_stream": {"columns": ["stream", "fps", "resolution", "kind", "frames", "delay_rate"],
                                "rows": per_stream,
                                "streams_with_late_frames": int(sum(1 for x in per_stream if x[5] > 0))},
-                "batches": len(sizes),
-                "mean_batch": round(float(np.mean(sizes)), 2), "max_batch_seen": int(max(sizes)),
+                "batches": batches, "hashed_frames": hashed,
+                "mean_batch": round((len(trace) + hashed) / max(batches, 1), 2),
                 "decrypt_check_ok": bool(ok), "status_ok": bool(status_ok),
-                "host_ms_per_batch": round(1000.0 * host_launch_s / max(len(sizes), 1), 3)}
+                "host_cpu_ms_per_batch": round(1000.0 * cpu / max(batches, 1), 3)}
 
-    # in flight per kind and resolution: --inflight (--inflight-4k at 3840x2160)
-    # (at 1: 8 device streams + 8 chain streams, within the hardware queues)
-    infl4k = args.inflight_4k or args.inflight
-    infl = lambda kind, c: max(1, infl4k if c == (3840, 2160) else args.inflight)
-    batched = one_run(trace, args.max_batch, infl, bool(args.hash_first))
+    batched = one_run(trace, args.max_batch, args.inflight, bool(args.hash_first))
     # The plain per-frame path cannot keep up with the offered load; it runs
     # the first --plain-frames arrivals of the same trace.
-    plain = one_run(trace[:plain_frames], 1, lambda kind, c: 1, False)
+    plain = one_run(trace[:plain_frames], 1, 1, False)
     offered = len(trace) / duration
     line = {"metric": "serving: p50/p99 arrival-to-completion latency (ms), frames/s", "value": batched["p99_ms"],
             "unit": "ms (p99)", "n_gpus": 1, "higher_is_better": False, "dtype": "u8", "data": "synthetic",
@@ -359,10 +322,10 @@ def serving_run(args, duration: float, plain_frames: int) -> dict:
                                    "640x480/1280x720/1920x1080/3840x2160, 30% decrypt streams, "
                                    f"{duration} s trace", "n": n, "offered_frames_per_s": round(offered, 1),
                        "hbm_budget_gb": args.hbm_budget_gb, "max_batch": args.max_batch,
-                       "inflight_batches_per_kind_and_resolution": f"{args.inflight} ({infl4k} at 3840x2160)",
+                       "inflight_batches_per_kind_and_resolution": args.inflight,
                        "batch_class": "resolution", "hash_first": bool(args.hash_first),
                        "parts": args.serve_parts, "side_streams": args.serve_side,
-                       "side_streams_1080p": args.serve_side_1080p},
+                       "loop": "vc_server_run_trace (native)"},
             "continuous_batching": batched, "plain_per_frame": plain}
     return line
 

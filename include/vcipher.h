@@ -381,6 +381,118 @@ int vc_batch_launch(vc_batch *batch, void *stream);
 /* Frees the batch (synchronises its device first).  NULL is a no-op. */
 void vc_batch_destroy(vc_batch *batch);
 
+/* ---- Serving: continuous batching of per-frame requests ----
+ * The paper's monitoring system (Sec. V) encrypts every stream frame by frame
+ * as frames arrive and reports latency and the delay rate (frames later than
+ * one frame interval).  A request is one frame of one stream to encrypt or
+ * decrypt.  The scheduler admits requests in arrival order while the device
+ * footprint of the requests in flight stays within hbm_budget (a request
+ * larger than the whole budget is admitted alone), launches a stream's frame
+ * t+1 only with or after frame t (the chain of Sec. II-A is serial per
+ * stream) and frames of one stream in one batch in sequence order, forms a
+ * batch (one library call) of one class from whatever has arrived whenever
+ * fewer than max_inflight batches of its kind and class are in flight, and at
+ * most max_batch requests per batch and max_stream_inflight frames of one
+ * stream in flight (0 = no limit).  With hash_first an encrypt request is
+ * first hashed in a "hash" batch (Sec. II-A's frame hash does not depend on
+ * the stream's previous frame), then encrypted in stream order with that
+ * hash.  Requests of different kinds are independent (a stream id names a
+ * chain of the sender or of the receiver). */
+enum { VC_REQ_ENCRYPT = 0, VC_REQ_DECRYPT = 1, VC_BATCH_HASH = 2 };
+
+typedef struct {
+    uint64_t tag;          /* the caller's id, returned with the completion */
+    int32_t kind;          /* VC_REQ_ENCRYPT or VC_REQ_DECRYPT */
+    uint32_t stream;       /* chain of the frame's video stream */
+    uint64_t seq;          /* 0, 1, 2, ... per (kind, stream) */
+    uint32_t w, h;         /* frame shape (3 channels) */
+    uint64_t cls;          /* batch class (vc_sched; the server sets it from w, h) */
+    uint64_t nbytes;       /* device bytes held while in flight (server: 0 = input,
+                              output and scratch, vc_scratch_per_frame) */
+    double arrival;        /* seconds on the caller's clock */
+    const uint8_t *frame;  /* device, h*w*3 (server) */
+    uint8_t *out;          /* device, h*w*3 (server) */
+    uint8_t *hash;         /* device, 32 bytes: written when encrypting, read when
+                              decrypting (the sender's H) (server) */
+} vc_request;
+
+typedef struct {
+    uint64_t tag;
+    double launched;   /* pump time of the request's first launch */
+    double done;       /* pump time at which its batch was seen complete */
+    int32_t hashed;    /* went through a hash batch first */
+    int32_t status;    /* VC_OK */
+} vc_completion;
+
+typedef struct {
+    uint64_t hbm_budget;
+    uint32_t max_inflight;         /* per kind and class (0 = 1) */
+    uint32_t max_batch;            /* 0 = 512 */
+    uint32_t max_stream_inflight;  /* 0 = no limit */
+    int32_t hash_first;
+} vc_sched_config;
+
+typedef struct {
+    uint32_t inflight_batches, pending, max_stream_inflight, completed_unpolled;
+    uint64_t inflight_bytes, batches_launched;
+} vc_sched_stats;
+
+/* The scheduling core over the caller's backend (host only; no device).
+ * vc_sched_pump(now): retires batches whose query returns 1 (their requests
+ * complete at `now`; hash batches move on to the ordered stage), then calls
+ * launch(user, kind, count, tags) for every batch it forms (kind:
+ * VC_REQ_ENCRYPT, VC_REQ_DECRYPT or VC_BATCH_HASH; returns a handle >= 0 or a
+ * negative status) and returns the number launched (or the first negative
+ * status).  vc_sched_poll returns completions in completion order.  Not
+ * thread-safe. */
+typedef struct vc_sched vc_sched;
+typedef int64_t (*vc_launch_fn)(void *user, int kind, size_t count, const uint64_t *tags);
+typedef int (*vc_query_fn)(void *user, int64_t handle);
+int vc_sched_create(const vc_sched_config *cfg, vc_sched **out);
+int vc_sched_submit(vc_sched *sched, const vc_request *req);
+int vc_sched_pump(vc_sched *sched, double now, vc_launch_fn launch, vc_query_fn query, void *user);
+size_t vc_sched_poll(vc_sched *sched, vc_completion *out, size_t max);
+int vc_sched_get_stats(const vc_sched *sched, vc_sched_stats *stats);
+int vc_sched_idle(const vc_sched *sched);
+void vc_sched_destroy(vc_sched *sched);
+
+/* The serving loop on the current GPU: the scheduler above with a backend of
+ * its own -- per class (one of the `nclasses` resolutions w, h given at
+ * creation) a sender and a receiver context (cipher_init with this key,
+ * max_streams chains, scratch_bytes of scratch, 0 = hbm_budget / nclasses
+ * but at least 1 GiB; vc_set_overlap(parts, side_streams, scratch_slots)
+ * when parts > 0), and per kind and class max_inflight device streams used
+ * in rotation.  A batch is one call of encrypt_frames (encrypt_frames_hashed
+ * after a hash batch), decrypt_frames or vc_hash_frames, with each request's
+ * own hash buffer; the key state and scratch stay resident.  The clock is
+ * seconds since creation (vc_server_clock).  vc_server_run_trace replays
+ * `count` requests sorted by arrival (seconds from the call), submitting each
+ * when the clock reaches it and pumping until all are done, and writes
+ * done[i] for reqs[i] (times relative to the call).  vc_server_reset sets
+ * every chain back to the key and every stream's next frame back to seq 0
+ * (VC_EBUSY unless idle).  Errors: VC_EINVAL for
+ * a shape that is not one of the classes, a stream out of range or NULL
+ * buffers; a failing library call is returned by pump. */
+typedef struct vc_server vc_server;
+typedef struct {
+    vc_sched_config sched;
+    uint32_t max_streams;
+    uint32_t parts, side_streams, scratch_slots;
+    uint64_t scratch_bytes;
+} vc_server_config;
+int vc_server_create(const vc_key *key, const uint32_t *classes, size_t nclasses, const vc_server_config *cfg,
+                     vc_server **out);
+double vc_server_clock(const vc_server *server);
+int vc_server_submit(vc_server *server, const vc_request *req);
+int vc_server_pump(vc_server *server);
+size_t vc_server_poll(vc_server *server, vc_completion *out, size_t max);
+int vc_server_idle(vc_server *server);
+int vc_server_get_stats(vc_server *server, vc_sched_stats *stats);
+int vc_server_run_trace(vc_server *server, size_t count, const vc_request *reqs, vc_completion *done);
+int vc_server_reset(vc_server *server);
+int vc_server_status(vc_server *server);
+void vc_server_destroy(vc_server *server);
+
 /* vc_bandwidth_probe: a measurement helper outside the cipher -- the
  * streaming ceiling that the confusion kernels' HBM rates are compared with.
  * kind 0 copies `bytes` from a to out; kind 1 writes out = a ^ b (two reads

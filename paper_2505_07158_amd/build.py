@@ -23,7 +23,8 @@ BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libvcipher.so")
 ARCH = os.environ.get("VC_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["vc_sha256.hip", "vc_keysched.hip", "vc_confuse.hip", "vc_shift.hip", "vc_stats.hip", "vc_api.hip"]
+SOURCES = ["vc_sha256.hip", "vc_keysched.hip", "vc_confuse.hip", "vc_shift.hip", "vc_stats.hip", "vc_api.hip",
+           "vc_serve.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++20", "-fPIC",

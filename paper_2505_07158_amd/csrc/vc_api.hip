@@ -353,6 +353,7 @@ struct CallArgs {
     const vc_shape *shapes;
     const uint8_t *hashes;       // H in (decrypt, keysched)
     uint8_t *hashes_out;         // H out (encrypt, hash)
+    uint8_t *const *hash_ptrs;   // per-frame H (32 bytes each) in place of hashes / hashes_out
     uint8_t *const *out;
     const uint16_t *const *dbgD;  // debug confuse inputs
     const uint8_t *const *dbgB;
@@ -477,8 +478,9 @@ void build_plan(const vc_cipher *ctx, const CallArgs &a, bool keysched_scratch, 
             d.w = s.w;
             d.h = s.h;
             d.L = frame_bytes(s);
-            d.hash = a.hashes_out ? a.hashes_out + 32 * f
-                                  : const_cast<uint8_t *>(a.hashes ? a.hashes + 32 * f : nullptr);
+            d.hash = a.hash_ptrs    ? a.hash_ptrs[f]
+                     : a.hashes_out ? a.hashes_out + 32 * f
+                                    : const_cast<uint8_t *>(a.hashes ? a.hashes + 32 * f : nullptr);
             d.IR = nullptr;
             d.D = nullptr;
             d.B = nullptr;
@@ -1061,6 +1063,29 @@ int decrypt_frames(vc_cipher *ctx, size_t count, const uint8_t *const *frames, c
     a.stream = static_cast<hipStream_t>(stream);
     return locked_call(ctx, a);
 }
+
+}  // extern "C"
+
+int vc::call_frames(vc_cipher *ctx, CallKind kind, size_t count, const uint8_t *const *frames, const vc_shape *shapes,
+                    uint8_t *const *hash_ptrs, uint8_t *const *out, hipStream_t stream) {
+    if (count && (!frames || !shapes || !hash_ptrs || (kind != CallKind::Hash && !out))) return VC_EINVAL;
+    for (size_t f = 0; f < count; ++f)
+        if (!hash_ptrs[f]) return VC_EINVAL;
+    CallArgs a{};
+    a.op = kind == CallKind::Encrypt         ? Op::Encrypt
+           : kind == CallKind::EncryptHashed ? Op::EncryptHashed
+           : kind == CallKind::Decrypt       ? Op::Decrypt
+                                             : Op::Hash;
+    a.count = count;
+    a.in = frames;
+    a.shapes = shapes;
+    a.hash_ptrs = hash_ptrs;
+    a.out = kind == CallKind::Hash ? nullptr : out;
+    a.stream = stream;
+    return locked_call(ctx, a);
+}
+
+extern "C" {
 
 int vc_hash_frames(vc_cipher *ctx, size_t count, const uint8_t *const *frames, const vc_shape *shapes,
                    uint8_t *hashes, void *stream) {

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/vcipher.h"
+
 namespace vc {
 
 // Pointers read out of descriptors are generic (flat) to the compiler;
@@ -161,6 +163,14 @@ hipError_t launch_frame_diff(const StatFrame *d_a, const StatFrame *d_b, uint32_
 // 16-byte aligned pointers), one 16-byte word per thread.
 hipError_t launch_stream_probe(int kind, const uint8_t *a, const uint8_t *b, uint8_t *out, uint64_t bytes,
                                hipStream_t s);
+
+// A library call (encrypt_frames, encrypt_frames_hashed, decrypt_frames or
+// vc_hash_frames) with a 32-byte hash buffer of its own for every frame
+// instead of one contiguous array; for the serving core, whose requests
+// each carry their own hash buffer.  Same validation and errors.
+enum class CallKind { Encrypt, EncryptHashed, Decrypt, Hash };
+int call_frames(vc_cipher *ctx, CallKind kind, size_t count, const uint8_t *const *frames, const vc_shape *shapes,
+                uint8_t *const *hash_ptrs, uint8_t *const *out, hipStream_t stream);
 
 // A wave of SHA-256 compression or of the key-stream integrator issues an
 // instruction almost every cycle, so two such waves on one SIMD each run at

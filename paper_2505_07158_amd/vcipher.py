@@ -40,6 +40,38 @@ class VcError(RuntimeError):
         self.status = status
 
 
+class VcRequest(C.Structure):
+    """vc_request: one frame of one stream to encrypt (kind 0) or decrypt (kind 1)."""
+    _fields_ = [("tag", C.c_uint64), ("kind", C.c_int32), ("stream", C.c_uint32), ("seq", C.c_uint64),
+                ("w", C.c_uint32), ("h", C.c_uint32), ("cls", C.c_uint64), ("nbytes", C.c_uint64),
+                ("arrival", C.c_double), ("frame", C.c_void_p), ("out", C.c_void_p), ("hash", C.c_void_p)]
+
+
+class VcCompletion(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("launched", C.c_double), ("done", C.c_double), ("hashed", C.c_int32),
+                ("status", C.c_int32)]
+
+
+class VcSchedConfig(C.Structure):
+    _fields_ = [("hbm_budget", C.c_uint64), ("max_inflight", C.c_uint32), ("max_batch", C.c_uint32),
+                ("max_stream_inflight", C.c_uint32), ("hash_first", C.c_int32)]
+
+
+class VcSchedStats(C.Structure):
+    _fields_ = [("inflight_batches", C.c_uint32), ("pending", C.c_uint32), ("max_stream_inflight", C.c_uint32),
+                ("completed_unpolled", C.c_uint32), ("inflight_bytes", C.c_uint64),
+                ("batches_launched", C.c_uint64)]
+
+
+class VcServerConfig(C.Structure):
+    _fields_ = [("sched", VcSchedConfig), ("max_streams", C.c_uint32), ("parts", C.c_uint32),
+                ("side_streams", C.c_uint32), ("scratch_slots", C.c_uint32), ("scratch_bytes", C.c_uint64)]
+
+
+LAUNCH_FN = C.CFUNCTYPE(C.c_int64, C.c_void_p, C.c_int, C.c_size_t, C.POINTER(C.c_uint64))
+QUERY_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int64)
+
+
 def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2505_07158_amd.build`")
@@ -84,6 +116,34 @@ def _load() -> C.CDLL:
     L.vc_batch_launch.restype = C.c_int
     L.vc_batch_destroy.argtypes = [vp]
     L.vc_batch_destroy.restype = None
+    L.vc_sched_create.argtypes = [C.POINTER(VcSchedConfig), C.POINTER(vp)]
+    L.vc_sched_submit.argtypes = [vp, C.POINTER(VcRequest)]
+    L.vc_sched_pump.argtypes = [vp, C.c_double, LAUNCH_FN, QUERY_FN, vp]
+    L.vc_sched_poll.argtypes = [vp, C.POINTER(VcCompletion), C.c_size_t]
+    L.vc_sched_poll.restype = C.c_size_t
+    L.vc_sched_get_stats.argtypes = [vp, C.POINTER(VcSchedStats)]
+    L.vc_sched_idle.argtypes = [vp]
+    L.vc_sched_destroy.argtypes = [vp]
+    L.vc_sched_destroy.restype = None
+    L.vc_server_create.argtypes = [C.POINTER(VcKey), C.POINTER(C.c_uint32), C.c_size_t, C.POINTER(VcServerConfig),
+                                   C.POINTER(vp)]
+    L.vc_server_clock.argtypes = [vp]
+    L.vc_server_clock.restype = C.c_double
+    L.vc_server_submit.argtypes = [vp, C.POINTER(VcRequest)]
+    L.vc_server_pump.argtypes = [vp]
+    L.vc_server_poll.argtypes = [vp, C.POINTER(VcCompletion), C.c_size_t]
+    L.vc_server_poll.restype = C.c_size_t
+    L.vc_server_idle.argtypes = [vp]
+    L.vc_server_get_stats.argtypes = [vp, C.POINTER(VcSchedStats)]
+    L.vc_server_run_trace.argtypes = [vp, C.c_size_t, C.POINTER(VcRequest), C.POINTER(VcCompletion)]
+    L.vc_server_reset.argtypes = [vp]
+    L.vc_server_status.argtypes = [vp]
+    L.vc_server_destroy.argtypes = [vp]
+    L.vc_server_destroy.restype = None
+    for name in ("vc_sched_create", "vc_sched_submit", "vc_sched_pump", "vc_sched_get_stats", "vc_sched_idle",
+                 "vc_server_create", "vc_server_submit", "vc_server_pump", "vc_server_idle", "vc_server_get_stats",
+                 "vc_server_run_trace", "vc_server_reset", "vc_server_status"):
+        getattr(L, name).restype = C.c_int
     L.vc_bandwidth_probe.argtypes = [C.c_int, vp, vp, vp, C.c_size_t, vp]
     L.vc_bandwidth_probe.restype = C.c_int
     L.vc_max_frame_height.argtypes = [vp]

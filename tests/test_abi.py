@@ -82,3 +82,34 @@ def test_nonfinite_key_and_zero_streams_rejected():
         with pytest.raises(V.VcError) as e:
             V.cipher_init(key, streams, 0)
         assert e.value.status == V.VC_EINVAL
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every struct the Python binding mirrors has the header's size and
+    field offsets (a host program built with gcc prints them)."""
+    import shutil
+    import subprocess
+    from paper_2505_07158_amd import vcipher as V
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not found")
+    mirrored = {"vc_key": V.VcKey, "vc_shape": V.VcShape, "vc_request": V.VcRequest,
+                "vc_completion": V.VcCompletion, "vc_sched_config": V.VcSchedConfig,
+                "vc_sched_stats": V.VcSchedStats, "vc_server_config": V.VcServerConfig}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "vcipher.h"', "int main(void) {"]
+    for cname, py in mirrored.items():
+        lines.append(f'printf("{cname} sizeof %zu\\n", sizeof({cname}));')
+        for field, _ in py._fields_:
+            lines.append(f'printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = {}
+    for ln in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.splitlines():
+        cname, field, value = ln.split()
+        got[(cname, field)] = int(value)
+    for cname, py in mirrored.items():
+        assert got[(cname, "sizeof")] == C.sizeof(py), cname
+        for field, _ in py._fields_:
+            assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
