@@ -138,8 +138,13 @@ hipError_t launch_shift(int decrypt, int pass, const FrameDesc *d_desc, uint32_t
 // for height h, 0 if none.
 uint32_t shift_max_strip(uint32_t h, uint32_t lds_bytes);
 // True when the row pass stages its rows in LDS for frames of width w (the
-// only form that reads or writes the strip-major intermediate image).
+// forms that read or write the strip-major intermediate image).
 bool shift_rows_staged(uint32_t w, uint32_t lds_bytes);
+// True when the row pass runs in its planar form (16 pixels per item, the
+// rows split into channel planes in LDS): alignment class 2, w a multiple
+// of 16, and one row with its planes fits lds_bytes.  Either staged form
+// reads and writes the strip-major intermediate image.
+bool shift_rows_planar(uint32_t w, int align, uint32_t lds_bytes);
 // Layout of the intermediate image for frames of width w whose column pass
 // uses strips of `strip` bytes under alignment class `align`: the strip
 // width when X is strip-major (FrameDesc::xstrip), else 0 (row-major).

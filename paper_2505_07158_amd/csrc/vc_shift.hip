@@ -278,11 +278,295 @@ __global__ __launch_bounds__(kRowThreads) void row_shift(const FrameDesc *__rest
 }
 
 // ----------------------------------------------------------------------
+// Planar row pass (rows of a multiple of 16 pixels, frames and outputs
+// 16-byte aligned).  The byte-wise form above spends most of its time on
+// per-byte LDS reads and index arithmetic; here one item is 16 pixels (48
+// bytes) of one row:
+//   1. the item's 48 bytes are loaded, split into the three channels with
+//      byte permutes and stored as LDS channel planes (w bytes each,
+//      followed by a copy of the plane's first 16 bytes, so that a window
+//      that runs past the end of the row continues at its start);
+//   2. the item makes its 16 output bytes of each channel c: they are bits
+//      s .. s+127 of the channel's bit row, s = (128 g + sh_c) mod 8w for
+//      item g, i.e. four v_alignbit of five plane dwords from byte
+//      (s >> 3) & ~3 on, at bit offset s mod 32; byte permutes interleave
+//      the channels again and the item stores 48 bytes.
+// ----------------------------------------------------------------------
+constexpr uint32_t kPlanePad = 16;
+
+__host__ __device__ inline uint32_t plane_stride(uint32_t w) { return w + kPlanePad; }
+// LDS of a planar workgroup of R rows: one buffer that holds in turn the
+// rows, their channel planes and the shifted rows, then the shift table.
+constexpr uint32_t kPlanarItems = 4;  // items per thread at most (registers across barriers)
+__host__ __device__ inline uint64_t planar_lds_bytes(uint32_t w, uint32_t R) {
+    return 3ull * R * plane_stride(w) + kRowShiftTable;
+}
+// Rows per planar workgroup: the most (4, 2 or 1) whose items fit the
+// threads' registers and whose LDS fits lds_limit; 0 if none.
+__host__ __device__ inline uint32_t planar_rows(uint32_t w, uint32_t lds_limit) {
+    for (uint32_t R = kRowsPerGroup; R >= 1; R /= 2)
+        if (static_cast<uint64_t>(R) * (w / 16) <= kRowThreads * kPlanarItems && planar_lds_bytes(w, R) <= lds_limit)
+            return R;
+    return 0;
+}
+
+// Byte permutes with compile-time selectors: dword k of the result is byte
+// B_k of the little-endian 12-dword array s.  v_perm_b32 picks from the
+// 64-bit pair (first operand : second operand); 0x0C gives a zero byte.
+constexpr int first_other(int a, int b, int c, int d, int x, int y) {
+    return (a != x && a != y) ? a : (b != x && b != y) ? b : (c != x && c != y) ? c : (d != x && d != y) ? d : -1;
+}
+constexpr uint32_t sel_two(const int (&B)[4], int lo, int hi) {
+    uint32_t sel = 0;
+    for (int k = 0; k < 4; ++k) {
+        const int dw = B[k] / 4, by = B[k] % 4;
+        const uint32_t v = dw == lo ? by : dw == hi ? 4 + by : 0x0C;
+        sel |= v << (8 * k);
+    }
+    return sel;
+}
+constexpr uint32_t sel_third(const int (&B)[4], int third) {
+    uint32_t sel = 0;
+    for (int k = 0; k < 4; ++k) {
+        const int dw = B[k] / 4, by = B[k] % 4;
+        const uint32_t v = dw == third ? 4 + by : k;
+        sel |= v << (8 * k);
+    }
+    return sel;
+}
+template <int B0, int B1, int B2, int B3>
+__device__ __forceinline__ uint32_t gather4(const uint32_t (&s)[12]) {
+    constexpr int B[4] = {B0, B1, B2, B3};
+    constexpr int d0 = B0 / 4;
+    constexpr int d1r = first_other(B0 / 4, B1 / 4, B2 / 4, B3 / 4, d0, d0);
+    constexpr int d1 = d1r < 0 ? d0 : d1r;
+    constexpr int d2 = first_other(B0 / 4, B1 / 4, B2 / 4, B3 / 4, d0, d1);
+    uint32_t r = __builtin_amdgcn_perm(s[d1], s[d0], sel_two(B, d0, d1));
+    if constexpr (d2 >= 0) r = __builtin_amdgcn_perm(s[d2], r, sel_third(B, d2));
+    return r;
+}
+
+// 48 interleaved bytes (pixel p, channel c at byte 3p + c) -> three planes
+// of 16 bytes (plane c dword m = channel c of pixels 4m .. 4m+3), and back.
+template <int C, int M>
+__device__ __forceinline__ uint32_t plane_dword(const uint32_t (&s)[12]) {
+    return gather4<12 * M + C, 12 * M + C + 3, 12 * M + C + 6, 12 * M + C + 9>(s);
+}
+template <int M>
+__device__ __forceinline__ uint32_t pixel_dword(const uint32_t (&p)[12]) {
+    // byte b = 4M + x is pixel b / 3, channel b % 3: plane dword 4c + pixel / 4
+    constexpr int b0 = 4 * M, b1 = b0 + 1, b2 = b0 + 2, b3 = b0 + 3;
+    return gather4<4 * (4 * (b0 % 3) + b0 / 12) + (b0 / 3) % 4, 4 * (4 * (b1 % 3) + b1 / 12) + (b1 / 3) % 4,
+                   4 * (4 * (b2 % 3) + b2 / 12) + (b2 / 3) % 4, 4 * (4 * (b3 % 3) + b3 / 12) + (b3 / 3) % 4>(p);
+}
+__device__ __forceinline__ void to_planes(const uint32_t (&s)[12], uint32_t (&p)[12]) {
+    p[0] = plane_dword<0, 0>(s); p[1] = plane_dword<0, 1>(s); p[2] = plane_dword<0, 2>(s); p[3] = plane_dword<0, 3>(s);
+    p[4] = plane_dword<1, 0>(s); p[5] = plane_dword<1, 1>(s); p[6] = plane_dword<1, 2>(s); p[7] = plane_dword<1, 3>(s);
+    p[8] = plane_dword<2, 0>(s); p[9] = plane_dword<2, 1>(s); p[10] = plane_dword<2, 2>(s); p[11] = plane_dword<2, 3>(s);
+}
+__device__ __forceinline__ void to_pixels(const uint32_t (&p)[12], uint32_t (&s)[12]) {
+    s[0] = pixel_dword<0>(p); s[1] = pixel_dword<1>(p); s[2] = pixel_dword<2>(p); s[3] = pixel_dword<3>(p);
+    s[4] = pixel_dword<4>(p); s[5] = pixel_dword<5>(p); s[6] = pixel_dword<6>(p); s[7] = pixel_dword<7>(p);
+    s[8] = pixel_dword<8>(p); s[9] = pixel_dword<9>(p); s[10] = pixel_dword<10>(p); s[11] = pixel_dword<11>(p);
+}
+
+// 16-byte word k of the run of rows r0 .. r0+nr-1 of X, in memory order:
+// its byte offset in X and in an LDS copy of those rows (row-major, rows
+// of rb bytes).  Row-major X: the rows are one run.  Strip-major X (strips
+// of xs = 2^sl bytes, ns of them): strip s holds the rows' segments of sbw
+// bytes as one run of nr * sbw bytes (every strip but the last has nr *
+// xs / 16 words).
+struct XRun {
+    uint32_t rb, h, r0, nr, xs, sl, ns, cps, cps_shift;
+    __device__ __forceinline__ XRun(uint32_t rb_, uint32_t h_, uint32_t r0_, uint32_t nr_, uint32_t xs_)
+        : rb(rb_), h(h_), r0(r0_), nr(nr_), xs(xs_) {
+        sl = xs ? static_cast<uint32_t>(__builtin_ctz(xs)) : 0;
+        ns = xs ? (rb + xs - 1) >> sl : 1;
+        cps = xs ? nr * (xs / 16) : 0;
+        // a power of two when nr is (every workgroup but a frame's last)
+        cps_shift = (cps && (cps & (cps - 1)) == 0) ? static_cast<uint32_t>(__builtin_ctz(cps)) : 32;
+    }
+    __device__ __forceinline__ void word(uint32_t k, uint64_t &x, uint32_t &lds) const {
+        if (!xs) {
+            x = static_cast<uint64_t>(r0) * rb + 16 * k;
+            lds = 16 * k;
+            return;
+        }
+        uint32_t st = cps_shift < 32 ? k >> cps_shift : k / cps;
+        st = st < ns - 1 ? st : ns - 1;
+        const uint32_t k0 = st << sl, sbw = (rb - k0 < xs) ? rb - k0 : xs;
+        const uint32_t within = k - st * cps;
+        uint32_t rr, e;
+        if (sbw == xs) {
+            rr = within >> (sl - 4);
+            e = within & (xs / 16 - 1);
+        } else {
+            rr = within / (sbw / 16);
+            e = within - rr * (sbw / 16);
+        }
+        x = static_cast<uint64_t>(k0) * h + static_cast<uint64_t>(r0) * sbw + 16 * within;
+        lds = rr * rb + k0 + 16 * e;
+    }
+};
+
+// One workgroup shifts R = rpg rows (at most kRowsPerGroup; 256 threads,
+// at most NI items each, NI <= kPlanarItems: fewer registers when rows are
+// short); one LDS buffer serves every phase:
+//   A. the rows are staged (row-major, 16-byte loads in memory order of the
+//      source, six in flight per thread);
+//   B. each item (16 pixels of a row) takes its 48 bytes into registers;
+//      after a barrier they are split into the channel planes, written over
+//      the rows;
+//   C. each item shifts its 16 bytes per channel out of the planes and
+//      interleaves them in registers; after a barrier they are written back
+//      as rows;
+//   D. the shifted rows are copied out in memory order of the destination
+//      (16-byte stores, whole runs of rpg rows of each strip when X is
+//      strip-major).
+template <bool INV, uint32_t NI>
+__global__ __launch_bounds__(kRowThreads) void row_shift_planar(const FrameDesc *__restrict__ desc, uint32_t first,
+                                                              uint32_t nframes, Geometry geo,
+                                                              uint32_t groups_per_frame, uint32_t rpg) {
+    extern __shared__ __align__(16) uint8_t lds[];
+    const uint32_t fl = blockIdx.x / groups_per_frame, grp = blockIdx.x - fl * groups_per_frame;
+    if (fl >= nframes) return;
+    const FrameDesc d = desc[first + fl];
+    const uint32_t w = geo.w, h = geo.h, W8 = geo.W8, rb = geo.row_bytes;
+    const uint32_t G = w / 16, ps = plane_stride(w);
+    const uint32_t r0 = grp * rpg;
+    const uint32_t nr = (h - r0 < rpg) ? h - r0 : rpg;
+    const uint32_t items = nr * G, n16 = nr * (rb / 16);
+    uint8_t *rows = lds;    // row rr at rr * rb
+    uint8_t *planes = lds;  // plane (rr, c) at (3 rr + c) * ps
+    uint32_t(*shS)[3] = reinterpret_cast<uint32_t(*)[3]>(lds + 3 * rpg * ps);
+    if (threadIdx.x < nr) row_shifts(gmem(d.D), r0 + threadIdx.x, h, geo, INV, shS[threadIdx.x]);
+    const VC_GLOBAL uint8_t *__restrict__ src = gmem(INV ? d.X : d.in);
+    VC_GLOBAL uint8_t *__restrict__ dst = gmem(INV ? d.out : d.X);
+    const XRun xr(rb, h, r0, nr, d.xstrip);
+    // A. stage
+    if (INV) {
+        stage16(
+            n16,
+            [&](uint32_t k) {
+                uint64_t x;
+                uint32_t l;
+                xr.word(k, x, l);
+                return reinterpret_cast<const VC_GLOBAL u32x4 *>(src + x);
+            },
+            [&](uint32_t k) {
+                uint64_t x;
+                uint32_t l;
+                xr.word(k, x, l);
+                return reinterpret_cast<u32x4 *>(rows + l);
+            });
+    } else {
+        const VC_GLOBAL u32x4 *s0 = reinterpret_cast<const VC_GLOBAL u32x4 *>(src + static_cast<uint64_t>(r0) * rb);
+        stage16(
+            n16, [&](uint32_t k) { return s0 + k; }, [&](uint32_t k) { return reinterpret_cast<u32x4 *>(rows) + k; });
+    }
+    __syncthreads();
+    // item j of this thread: it = threadIdx.x + j * kRowThreads, row rr, 16-pixel group g
+    uint32_t rrj[NI], gj[NI];
+#pragma unroll
+    for (uint32_t j = 0; j < NI; ++j) {
+        const uint32_t it = threadIdx.x + j * kRowThreads;
+        rrj[j] = static_cast<uint32_t>(it >= G) + (it >= 2 * G) + (it >= 3 * G);
+        gj[j] = it - rrj[j] * G;
+    }
+    u32x4 v[NI][3];
+    // B. rows -> registers -> channel planes
+#pragma unroll
+    for (uint32_t j = 0; j < NI; ++j)
+        if (threadIdx.x + j * kRowThreads < items) {
+            const u32x4 *q = reinterpret_cast<const u32x4 *>(rows + rrj[j] * rb + 48 * gj[j]);
+            v[j][0] = q[0];
+            v[j][1] = q[1];
+            v[j][2] = q[2];
+        }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < NI; ++j)
+        if (threadIdx.x + j * kRowThreads < items) {
+            uint32_t sw[12], p[12];
+#pragma unroll
+            for (uint32_t i = 0; i < 3; ++i) {
+                sw[4 * i] = v[j][i].x; sw[4 * i + 1] = v[j][i].y; sw[4 * i + 2] = v[j][i].z; sw[4 * i + 3] = v[j][i].w;
+            }
+            to_planes(sw, p);
+#pragma unroll
+            for (uint32_t c = 0; c < 3; ++c) {
+                uint8_t *pl = planes + (3 * rrj[j] + c) * ps;
+                const u32x4 x{p[4 * c], p[4 * c + 1], p[4 * c + 2], p[4 * c + 3]};
+                *reinterpret_cast<u32x4 *>(pl + 16 * gj[j]) = x;
+                if (gj[j] == 0) *reinterpret_cast<u32x4 *>(pl + w) = x;  // the wrap-around copy
+            }
+        }
+    __syncthreads();
+    // C. shift out of the planes and interleave -> registers -> rows
+#pragma unroll
+    for (uint32_t j = 0; j < NI; ++j)
+        if (threadIdx.x + j * kRowThreads < items) {
+            const uint32_t rr = rrj[j], g = gj[j];
+            uint32_t p[12], o[12];
+#pragma unroll
+            for (uint32_t c = 0; c < 3; ++c) {
+                uint32_t s = 128 * g + shS[rr][c];  // 128 g < 8w, sh < 8w
+                if (s >= W8) s -= W8;
+                const uint32_t *a = reinterpret_cast<const uint32_t *>(planes + (3 * rr + c) * ps) + (s >> 5);
+                const uint32_t a0 = a[0], a1 = a[1], a2 = a[2], a3 = a[3], a4 = a[4];
+                const uint32_t t = s & 31;
+                p[4 * c] = __builtin_amdgcn_alignbit(a1, a0, t);
+                p[4 * c + 1] = __builtin_amdgcn_alignbit(a2, a1, t);
+                p[4 * c + 2] = __builtin_amdgcn_alignbit(a3, a2, t);
+                p[4 * c + 3] = __builtin_amdgcn_alignbit(a4, a3, t);
+            }
+            to_pixels(p, o);
+#pragma unroll
+            for (uint32_t i = 0; i < 3; ++i) v[j][i] = u32x4{o[4 * i], o[4 * i + 1], o[4 * i + 2], o[4 * i + 3]};
+        }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t j = 0; j < NI; ++j)
+        if (threadIdx.x + j * kRowThreads < items) {
+            u32x4 *q = reinterpret_cast<u32x4 *>(rows + rrj[j] * rb + 48 * gj[j]);
+            q[0] = v[j][0];
+            q[1] = v[j][1];
+            q[2] = v[j][2];
+        }
+    __syncthreads();
+    // D. copy out
+    if (INV) {
+        VC_GLOBAL u32x4 *d0 = reinterpret_cast<VC_GLOBAL u32x4 *>(dst + static_cast<uint64_t>(r0) * rb);
+        stage16(
+            n16, [&](uint32_t k) { return reinterpret_cast<const u32x4 *>(rows) + k; }, [&](uint32_t k) { return d0 + k; });
+    } else {
+        stage16(
+            n16,
+            [&](uint32_t k) {
+                uint64_t x;
+                uint32_t l;
+                xr.word(k, x, l);
+                return reinterpret_cast<const u32x4 *>(rows + l);
+            },
+            [&](uint32_t k) {
+                uint64_t x;
+                uint32_t l;
+                xr.word(k, x, l);
+                return reinterpret_cast<VC_GLOBAL u32x4 *>(dst + x);
+            });
+    }
+}
+
+// ----------------------------------------------------------------------
 // Column pass
 // ----------------------------------------------------------------------
 // LDS: the strip (h rows of at most SB bytes), then the strip's column
 // distances (SB words: the source-row offset of each byte column).
-__host__ __device__ inline uint32_t col_dv_off(uint32_t h, uint32_t SB) { return align16(h * SB); }
+// Strips of 16 bytes or more keep each staged row at a stride of SB + 4
+// bytes (an odd number of dwords), so that the gather's lanes, which read
+// the same byte column of consecutive rows, fall in different LDS banks.
+__host__ __device__ constexpr uint32_t col_row_stride(uint32_t SB) { return SB >= 16 ? SB + 4 : SB; }
+__host__ __device__ inline uint32_t col_dv_off(uint32_t h, uint32_t SB) { return align16(h * col_row_stride(SB)); }
 __host__ __device__ inline uint32_t col_lds_bytes(uint32_t h, uint32_t SB) { return col_dv_off(h, SB) + 4 * SB; }
 
 // Byte columns k0 .. k0 + sb - 1 of the strip: dvS[kk] = d_v mod h of the
@@ -297,6 +581,15 @@ __device__ __forceinline__ void col_distances(const VC_GLOBAL uint16_t *D, const
         const uint32_t dv = mod_u16(D[3 * h + c * w + j], geo.mod_h);
         dvS[kk] = inv ? (dv ? h - dv : 0) : dv;
     }
+}
+
+// A 16-byte word to a 4-byte aligned LDS address (the padded staged rows).
+__device__ __forceinline__ void put16(uint8_t *p, const u32x4 &v) {
+    uint32_t *q = reinterpret_cast<uint32_t *>(p);
+    q[0] = v.x;
+    q[1] = v.y;
+    q[2] = v.z;
+    q[3] = v.w;
 }
 
 // 16-byte column pass: rows of a multiple of 16 bytes, frames, outputs and
@@ -321,7 +614,7 @@ __global__ __launch_bounds__(NT) void col_shift_v(const FrameDesc *__restrict__ 
     const uint32_t h = geo.h, rb = geo.row_bytes;
     const uint32_t k0 = strip * SB;
     const uint32_t sb = (rb - k0 < static_cast<uint32_t>(SB)) ? rb - k0 : SB;  // a multiple of 16
-    const uint32_t nq = sb >> 4;
+    const uint32_t nq = sb >> 4, sbp = sb + 4;  // staged row stride: col_row_stride
     const uint32_t RP = NT / nq;  // rows per pass
     const uint32_t q = threadIdx.x % nq, i0 = threadIdx.x / nq;
     const uint32_t np = (i0 < RP && i0 < h) ? (h - i0 + RP - 1) / RP : 0;  // rows of this thread
@@ -337,17 +630,16 @@ __global__ __launch_bounds__(NT) void col_shift_v(const FrameDesc *__restrict__ 
 #pragma unroll
         for (uint32_t u = 0; u < U; ++u)
             if (u < np) b[u] = *reinterpret_cast<const VC_GLOBAL u32x4 *>(Bq + static_cast<uint64_t>(i0 + u * RP) * rb);
-        const uint32_t n16 = h * nq;
-        const VC_GLOBAL u32x4 *X4 = reinterpret_cast<const VC_GLOBAL u32x4 *>(Xs);
-        u32x4 *S4 = reinterpret_cast<u32x4 *>(S);
-        for (uint32_t k = threadIdx.x; k < n16; k += 4 * NT) {
+        // word q of rows i0, i0 + RP, ...: a wave reads a contiguous run of X
+        const VC_GLOBAL u32x4 *X4 = reinterpret_cast<const VC_GLOBAL u32x4 *>(Xs) + q;
+        for (uint32_t p0 = 0; p0 < np; p0 += 4) {
             u32x4 v[4];
 #pragma unroll
             for (uint32_t u = 0; u < 4; ++u)
-                if (k + u * NT < n16) v[u] = X4[k + u * NT];
+                if (p0 + u < np) v[u] = X4[(i0 + (p0 + u) * RP) * nq];
 #pragma unroll
             for (uint32_t u = 0; u < 4; ++u)
-                if (k + u * NT < n16) S4[k + u * NT] = v[u];
+                if (p0 + u < np) put16(S + (i0 + (p0 + u) * RP) * sbp + 16 * q, v[u]);
         }
     } else {
         const VC_GLOBAL uint8_t *Cq = gmem(d.in) + k0 + 16 * q;
@@ -364,7 +656,7 @@ __global__ __launch_bounds__(NT) void col_shift_v(const FrameDesc *__restrict__ 
 #pragma unroll
             for (uint32_t u = 0; u < U; ++u)
                 if (p0 + u < np)
-                    *reinterpret_cast<u32x4 *>(S + (i0 + (p0 + u) * RP) * sb + 16 * q) = c[u] ^ b[u];
+                    put16(S + (i0 + (p0 + u) * RP) * sbp + 16 * q, c[u] ^ b[u]);
         }
     }
     __syncthreads();
@@ -377,9 +669,9 @@ __global__ __launch_bounds__(NT) void col_shift_v(const FrameDesc *__restrict__ 
     for (uint32_t m = 0; m < 16; ++m) {
         const uint32_t kk = 16 * q + m, dv = dvS[kk];
         const uint32_t r = (i0 >= dv) ? i0 - dv : i0 + h - dv;
-        a[m] = r * sb + kk;
+        a[m] = r * sbp + kk;
     }
-    const uint32_t stepA = (RP % h) * sb, wrapA = h * sb;
+    const uint32_t stepA = (RP % h) * sbp, wrapA = h * sbp;
     VC_GLOBAL uint8_t *Oq = INV ? Xs + 16 * q : gmem(d.out) + k0 + 16 * q;
     const uint32_t ostride = INV ? sb : rb;
     for (uint32_t p0 = 0; p0 < np; p0 += U) {
@@ -519,8 +811,23 @@ hipError_t launch_col(const FrameDesc *d_desc, uint32_t first, uint32_t count, c
 }
 
 template <bool INV>
-hipError_t launch_row(const FrameDesc *d_desc, uint32_t first, uint32_t count, const Geometry &g, bool aligned,
+hipError_t launch_row(const FrameDesc *d_desc, uint32_t first, uint32_t count, const Geometry &g, int align,
                       uint32_t lds_limit, hipStream_t s) {
+    const bool aligned = align >= 1;
+    if (shift_rows_planar(g.w, align, lds_limit)) {
+        const uint32_t R = planar_rows(g.w, lds_limit);
+        const uint32_t per_frame = (g.h + R - 1) / R;
+        const uint64_t groups = static_cast<uint64_t>(count) * per_frame;
+        if (groups > 0x7FFFFFFFull) return hipErrorInvalidValue;
+        const uint32_t lds = static_cast<uint32_t>(planar_lds_bytes(g.w, R));
+        if (R * (g.w / 16) <= 2 * kRowThreads)
+            hipLaunchKernelGGL((row_shift_planar<INV, 2>), dim3(static_cast<uint32_t>(groups)), dim3(kRowThreads), lds,
+                               s, d_desc, first, count, g, per_frame, R);
+        else
+            hipLaunchKernelGGL((row_shift_planar<INV, kPlanarItems>), dim3(static_cast<uint32_t>(groups)),
+                               dim3(kRowThreads), lds, s, d_desc, first, count, g, per_frame, R);
+        return hipGetLastError();
+    }
     const uint32_t per_frame = (g.h + kRowsPerGroup - 1) / kRowsPerGroup;
     const uint64_t groups = static_cast<uint64_t>(count) * per_frame;
     if (groups > 0x7FFFFFFFull) return hipErrorInvalidValue;
@@ -576,6 +883,10 @@ bool shift_rows_staged(uint32_t w, uint32_t lds_bytes) {
     return kRowsPerGroup * lds_row + kRowShiftTable <= lds_bytes;
 }
 
+bool shift_rows_planar(uint32_t w, int align, uint32_t lds_bytes) {
+    return align >= 2 && w >= 16 && w % 16 == 0 && planar_rows(w, lds_bytes) > 0;
+}
+
 uint32_t shift_max_strip(uint32_t h, uint32_t lds_bytes) {
     uint32_t best = 0;
     for (uint32_t sb : kColStrips)
@@ -592,11 +903,17 @@ hipError_t shift_configure(uint32_t lds_limit) {
     if (e == hipSuccess) e = set_col_attr_sb<128>(lds_limit);
     if (e == hipSuccess) e = set_lds(&row_shift<false, true>, lds_limit);
     if (e == hipSuccess) e = set_lds(&row_shift<true, true>, lds_limit);
+    if (e == hipSuccess) e = set_lds(&row_shift_planar<false, 2>, lds_limit);
+    if (e == hipSuccess) e = set_lds(&row_shift_planar<true, 2>, lds_limit);
+    if (e == hipSuccess) e = set_lds(&row_shift_planar<false, kPlanarItems>, lds_limit);
+    if (e == hipSuccess) e = set_lds(&row_shift_planar<true, kPlanarItems>, lds_limit);
     return e;
 }
 
 uint32_t shift_xstrip(uint32_t w, uint32_t strip, int align, uint32_t lds_limit) {
-    if (align < 2 || strip < 16 || (3ull * w) % 16 != 0 || !shift_rows_staged(w, lds_limit)) return 0;
+    if (align < 2 || strip < 16 || (3ull * w) % 16 != 0 ||
+        !(shift_rows_staged(w, lds_limit) || shift_rows_planar(w, align, lds_limit)))
+        return 0;
     for (uint32_t sb : kColStrips)
         if (sb == strip) return strip;
     return 0;
@@ -615,8 +932,8 @@ hipError_t launch_shift(int decrypt, int pass, const FrameDesc *d_desc, uint32_t
     // encrypt: pass 0 = rows, pass 1 = columns; decrypt: pass 0 = columns, pass 1 = rows
     const bool rows = decrypt ? pass == 1 : pass == 0;
     if (rows)
-        return decrypt ? launch_row<true>(d_desc, first, count, g, align >= 1, lds_limit, s)
-                       : launch_row<false>(d_desc, first, count, g, align >= 1, lds_limit, s);
+        return decrypt ? launch_row<true>(d_desc, first, count, g, align, lds_limit, s)
+                       : launch_row<false>(d_desc, first, count, g, align, lds_limit, s);
     // the 16-byte kernels read or write X strip-major in this launch's
     // strips; the host lays X out so exactly when shift_xstrip says so
     const bool vec = shift_xstrip(w, t.strip, align, lds_limit) != 0;

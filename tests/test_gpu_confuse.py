@@ -15,7 +15,11 @@ pytestmark = pytest.mark.gpu
 
 SHAPES = [(1, 1), (1, 4), (2, 3), (3, 1), (5, 7), (4, 4), (8, 12), (17, 5), (64, 64), (33, 100),
           (100, 33), (480, 640), (481, 643), (720, 1280), (1080, 1920), (2, 2000), (2000, 3),
-          (3, 56000)]  # a row longer than the LDS: the row pass reads global memory
+          (3, 56000),  # a row longer than the LDS: the row pass reads global memory
+          # rows of a multiple of 16 pixels (the row pass's planar form): one
+          # 16-pixel item per row, two, 2 and 1 rows per workgroup, a last
+          # workgroup with fewer rows
+          (5, 16), (6, 32), (9, 2048), (7, 3840), (6, 20000)]
 
 
 def case(rng, h, w):
