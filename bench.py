@@ -54,9 +54,9 @@ def parse():
     ap.add_argument("--max-batch", type=int, default=256, help="serving: frames per batch at most")
     ap.add_argument("--plain-frames", type=int, default=400, help="serving: arrivals replayed one frame per launch")
     ap.add_argument("--inflight", type=int, default=1, help="serving: batches in flight per kind and resolution")
-    ap.add_argument("--hash-first", type=int, default=0,
+    ap.add_argument("--hash-first", type=int, default=1,
                     help="serving: 1 = hash each encrypt request on arrival, then chain/keystream/confusion in "
-                    "stream order (encrypt_frames_hashed); 0 = one encrypt_frames call per batch")
+                    "stream order (encrypt_frames_hashed; the default); 0 = one encrypt_frames call per batch")
     ap.add_argument("--serve-parts", type=int, default=1, help="serving: parts per call (vc_set_overlap)")
     ap.add_argument("--serve-side", type=int, default=0, help="serving: side streams per context (vc_set_overlap)")
     ap.add_argument("--steps", type=int, default=20)

@@ -112,17 +112,20 @@ int cipher_init(const vc_key *key, uint32_t max_streams, size_t scratch_bytes, v
 void cipher_destroy(vc_cipher *ctx);
 
 /* Encrypt `count` frames.  frames[f] (device, L bytes) is the plaintext,
- * out[f] (device, L bytes) receives the ciphertext, hashes (device,
- * count*32 bytes) receives each frame's H in FIPS 180-4 digest byte order;
- * the receiver needs H to decrypt (Sec. V: hashes travel with the frames).
+ * out[f] (device, L bytes) receives the ciphertext, hashes (count*32 bytes)
+ * receives each frame's H in FIPS 180-4 digest byte order; the receiver
+ * needs H to decrypt (Sec. V: hashes travel with the frames).  Hash buffers
+ * here and below may be device memory or pinned host memory
+ * (hipHostMalloc): the kernels write and read them in place; any other host
+ * memory is rejected with VC_EINVAL (vc_pointer_reachable).
  * out[f] must not overlap frames[f] (the permutation is a gather).
- * Errors: VC_EINVAL (shape, NULL, overlap), VC_EORDER (seq), VC_ENOMEM
- * (frame larger than the scratch), VC_EDEVICE. */
+ * Errors: VC_EINVAL (shape, NULL, overlap, hash buffer), VC_EORDER (seq),
+ * VC_ENOMEM (frame larger than the scratch), VC_EDEVICE. */
 int encrypt_frames(vc_cipher *ctx, size_t count, const uint8_t *const *frames,
                    const vc_shape *shapes, uint8_t *hashes, uint8_t *const *out,
                    void *stream);
 
-/* Decrypt `count` frames with the sender's hashes (device, count*32 bytes).
+/* Decrypt `count` frames with the sender's hashes (count*32 bytes).
  * frames[f] is ciphertext, out[f] receives the plaintext.  Same errors and
  * ordering rules as encrypt_frames. */
 int decrypt_frames(vc_cipher *ctx, size_t count, const uint8_t *const *frames,
@@ -162,8 +165,8 @@ int encrypt_frames_noalloc(vc_cipher *ctx, size_t count, const uint8_t *const *f
 
 /* encrypt_frames with the frame hashes already computed (by
  * vc_hash_frames on the same plaintext, possibly on another stream): runs
- * the key schedule and the confusion + XOR only.  hashes (device,
- * count*32 bytes) is read.  This lets a sender hash batch k+1 while batch k
+ * the key schedule and the confusion + XOR only.  hashes (count*32 bytes)
+ * is read.  This lets a sender hash batch k+1 while batch k
  * is being encrypted.  If a hash is not the one of Sec. II-A for its frame,
  * the receiver can still decrypt with it, but the output no longer follows
  * the paper's protocol.  Same errors and ordering rules as encrypt_frames. */
@@ -369,7 +372,7 @@ int vc_frame_diff(size_t count, const uint8_t *const *a, const uint8_t *const *b
  * caller orders a context's batch launches with its other calls (they share
  * its chain states), keeps every buffer alive while the batch exists, and
  * must not prepare a batch while another call of the context may be
- * running.  decrypt = 0: frames are plaintext, hashes (device, count*32)
+ * running.  decrypt = 0: frames are plaintext, hashes (count*32 bytes)
  * receive H; decrypt = 1: frames are ciphertext, hashes hold the sender's
  * H.  Tiling (autotuned or fixed) is taken at prepare time.  Kernel
  * profiling does not time batch launches.  Errors: as encrypt_frames, plus
@@ -412,7 +415,7 @@ typedef struct {
     double arrival;        /* seconds on the caller's clock */
     const uint8_t *frame;  /* device, h*w*3 (server) */
     uint8_t *out;          /* device, h*w*3 (server) */
-    uint8_t *hash;         /* device, 32 bytes: written when encrypting, read when
+    uint8_t *hash;         /* 32 bytes (device or pinned host): written when encrypting, read when
                               decrypting (the sender's H) (server) */
 } vc_request;
 
@@ -492,6 +495,13 @@ int vc_server_run_trace(vc_server *server, size_t count, const vc_request *reqs,
 int vc_server_reset(vc_server *server);
 int vc_server_status(vc_server *server);
 void vc_server_destroy(vc_server *server);
+
+/* 1 when the kernels can read and write [p, p + bytes) in place: device or
+ * managed memory, or pinned host memory that the device addresses at the
+ * same address (hipHostMalloc); 0 otherwise (pageable host memory, NULL,
+ * bytes == 0, or no device).  The calls above check their hash buffers with
+ * it before enqueuing anything.  Host only. */
+int vc_pointer_reachable(const void *p, size_t bytes);
 
 /* vc_bandwidth_probe: a measurement helper outside the cipher -- the
  * streaming ceiling that the confusion kernels' HBM rates are compared with.

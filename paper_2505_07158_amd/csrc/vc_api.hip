@@ -179,6 +179,31 @@ struct vc_cipher {
     std::mutex mu;
 };
 
+namespace vc {
+// True when [p, p + bytes) is memory the kernels can address as it is:
+// device or managed memory, or pinned host memory mapped at the same
+// address (hipHostMalloc).  Pageable host memory is not (no XNACK), and a
+// kernel touching it faults, so buffers the kernels access in place are
+// checked before anything is enqueued.
+bool reachable(const void *p, size_t bytes) {
+    if (!p || bytes == 0) return false;
+    const uint8_t *b = static_cast<const uint8_t *>(p);
+    for (const uint8_t *q : {b, b + (bytes - 1)}) {
+        hipPointerAttribute_t at{};
+        if (hipPointerGetAttributes(&at, q) != hipSuccess) {
+            (void)hipGetLastError();  // leave no error behind for the next launch check
+            return false;
+        }
+        const bool ok = at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged ||
+                        at.type == hipMemoryTypeUnified ||
+                        (at.type == hipMemoryTypeHost && at.devicePointer == static_cast<const void *>(q));
+        if (!ok) return false;
+    }
+    return true;
+}
+
+}  // namespace vc
+
 namespace {
 struct CallArgs;
 }
@@ -575,6 +600,17 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
             const uint64_t expect = (it == seq_next.end()) ? ctx->next_seq[s.stream] : it->second;
             if (s.seq != expect) return VC_EORDER;
             seq_next[s.stream] = expect + 1;
+        }
+    }
+    // hash buffers are read and written by the kernels in place: device
+    // memory or pinned host memory only (pageable memory would fault)
+    if (count) {
+        if (a.hash_ptrs) {
+            for (size_t f = 0; f < count; ++f)
+                if (!reachable(a.hash_ptrs[f], 32)) return VC_EINVAL;
+        } else {
+            const uint8_t *hb = a.hashes_out ? a.hashes_out : a.hashes;
+            if (hb && !reachable(hb, 32 * count)) return VC_EINVAL;
         }
     }
     // descriptors of a no-alloc call: frame descriptors, at most one stream
@@ -1637,6 +1673,8 @@ int vc_frame_diff(size_t count, const uint8_t *const *a, const uint8_t *const *b
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     return map_err(e);
 }
+
+int vc_pointer_reachable(const void *p, size_t bytes) { return vc::reachable(p, bytes) ? 1 : 0; }
 
 int vc_bandwidth_probe(int kind, const uint8_t *a, const uint8_t *b, uint8_t *out, size_t bytes, void *stream) {
     if ((kind != 0 && kind != 1) || !a || !out || (kind == 1 && !b) || bytes % 16) return VC_EINVAL;

@@ -173,6 +173,8 @@ hipError_t launch_stream_probe(int kind, const uint8_t *a, const uint8_t *b, uin
 // vc_hash_frames) with a 32-byte hash buffer of its own for every frame
 // instead of one contiguous array; for the serving core, whose requests
 // each carry their own hash buffer.  Same validation and errors.
+// Device-addressable buffer check (vc_pointer_reachable).
+bool reachable(const void *p, size_t bytes);
 enum class CallKind { Encrypt, EncryptHashed, Decrypt, Hash };
 int call_frames(vc_cipher *ctx, CallKind kind, size_t count, const uint8_t *const *frames, const vc_shape *shapes,
                 uint8_t *const *hash_ptrs, uint8_t *const *out, hipStream_t stream);

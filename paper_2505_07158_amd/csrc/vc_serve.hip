@@ -446,7 +446,7 @@ double vc_server_clock(const vc_server *srv) { return srv ? seconds_since(srv->t
 
 int vc_server_submit(vc_server *srv, const vc_request *req) {
     if (!srv || !req || (req->kind != KIND_ENC && req->kind != KIND_DEC) || !req->frame || !req->out || !req->hash ||
-        req->stream >= srv->max_streams)
+        req->stream >= srv->max_streams || !vc::reachable(req->hash, 32))
         return VC_EINVAL;
     std::unique_ptr<Req> r(new (std::nothrow) Req());
     if (!r) return VC_ENOMEM;

@@ -146,6 +146,8 @@ def _load() -> C.CDLL:
         getattr(L, name).restype = C.c_int
     L.vc_bandwidth_probe.argtypes = [C.c_int, vp, vp, vp, C.c_size_t, vp]
     L.vc_bandwidth_probe.restype = C.c_int
+    L.vc_pointer_reachable.argtypes = [vp, C.c_size_t]
+    L.vc_pointer_reachable.restype = C.c_int
     L.vc_max_frame_height.argtypes = [vp]
     L.vc_max_frame_height.restype = C.c_uint32
     L.vc_scratch_per_frame.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
@@ -250,12 +252,23 @@ def cipher_destroy(ctx: int) -> None:
     lib.cipher_destroy(C.c_void_p(ctx))
 
 
+def _hash_buffer_ok(hashes: torch.Tensor, count: int) -> bool:
+    """uint8, contiguous, at least count*32 bytes, on the device or in pinned host memory."""
+    return (hashes.dtype == torch.uint8 and hashes.is_contiguous() and hashes.numel() >= 32 * count
+            and (hashes.is_cuda or hashes.is_pinned()))
+
+
+def vc_pointer_reachable(t: torch.Tensor) -> bool:
+    """True when the library's kernels can access the tensor's memory in place."""
+    return bool(lib.vc_pointer_reachable(C.c_void_p(t.data_ptr()), t.numel() * t.element_size()))
+
+
 def encrypt_frames(ctx: int, frames: Sequence[torch.Tensor], streams: Sequence[int], seqs: Sequence[int],
                    hashes: torch.Tensor, out: Sequence[torch.Tensor],
                    stream: Optional[torch.cuda.Stream] = None) -> None:
     for t in list(frames) + list(out):
         _check_frame(t)
-    if hashes.dtype != torch.uint8 or not hashes.is_cuda or hashes.numel() < 32 * len(frames):
+    if not _hash_buffer_ok(hashes, len(frames)):
         raise ValueError("hashes must be a CUDA uint8 tensor of count*32 bytes")
     rc = lib.encrypt_frames(C.c_void_p(ctx), len(frames), _ptrs(frames), _shapes(frames, streams, seqs),
                             C.c_void_p(hashes.data_ptr()), _ptrs(out), C.c_void_p(_stream_handle(stream)))
@@ -267,7 +280,7 @@ def encrypt_frames_noalloc(ctx: int, frames: Sequence[torch.Tensor], streams: Se
                            stream: Optional[torch.cuda.Stream] = None) -> None:
     for t in list(frames) + list(out):
         _check_frame(t)
-    if hashes.dtype != torch.uint8 or not hashes.is_cuda or hashes.numel() < 32 * len(frames):
+    if not _hash_buffer_ok(hashes, len(frames)):
         raise ValueError("hashes must be a CUDA uint8 tensor of count*32 bytes")
     rc = lib.encrypt_frames_noalloc(C.c_void_p(ctx), len(frames), _ptrs(frames), _shapes(frames, streams, seqs),
                                     C.c_void_p(hashes.data_ptr()), _ptrs(out), C.c_void_p(_stream_handle(stream)))
@@ -279,7 +292,7 @@ def encrypt_frames_hashed(ctx: int, frames: Sequence[torch.Tensor], streams: Seq
                           stream: Optional[torch.cuda.Stream] = None) -> None:
     for t in list(frames) + list(out):
         _check_frame(t)
-    if hashes.dtype != torch.uint8 or not hashes.is_cuda or hashes.numel() < 32 * len(frames):
+    if not _hash_buffer_ok(hashes, len(frames)):
         raise ValueError("hashes must be a CUDA uint8 tensor of count*32 bytes")
     rc = lib.encrypt_frames_hashed(C.c_void_p(ctx), len(frames), _ptrs(frames), _shapes(frames, streams, seqs),
                                    C.c_void_p(hashes.data_ptr()), _ptrs(out), C.c_void_p(_stream_handle(stream)))
@@ -291,7 +304,7 @@ def decrypt_frames(ctx: int, frames: Sequence[torch.Tensor], streams: Sequence[i
                    stream: Optional[torch.cuda.Stream] = None) -> None:
     for t in list(frames) + list(out):
         _check_frame(t)
-    if hashes.dtype != torch.uint8 or not hashes.is_cuda or hashes.numel() < 32 * len(frames):
+    if not _hash_buffer_ok(hashes, len(frames)):
         raise ValueError("hashes must be a CUDA uint8 tensor of count*32 bytes")
     rc = lib.decrypt_frames(C.c_void_p(ctx), len(frames), _ptrs(frames), _shapes(frames, streams, seqs),
                             C.c_void_p(hashes.data_ptr()), _ptrs(out), C.c_void_p(_stream_handle(stream)))
@@ -341,7 +354,7 @@ class Batch:
                  seqs: Sequence[int], hashes: torch.Tensor, out: Sequence[torch.Tensor]):
         for t in list(frames) + list(out):
             _check_frame(t)
-        if hashes.dtype != torch.uint8 or not hashes.is_cuda or hashes.numel() < 32 * len(frames):
+        if not _hash_buffer_ok(hashes, len(frames)):
             raise ValueError("hashes must be a CUDA uint8 tensor of count*32 bytes")
         self._keep = (list(frames), hashes, list(out))
         h = C.c_void_p()

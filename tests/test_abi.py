@@ -113,3 +113,14 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert got[(cname, "sizeof")] == C.sizeof(py), cname
         for field, _ in py._fields_:
             assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
+
+
+def test_pointer_reachable_refuses_host_memory(lib):
+    """vc_pointer_reachable: pageable host memory, NULL and empty ranges are
+    not device-addressable (with or without a GPU)."""
+    lib.vc_pointer_reachable.argtypes = [C.c_void_p, C.c_size_t]
+    lib.vc_pointer_reachable.restype = C.c_int
+    buf = (C.c_uint8 * 64)()
+    assert lib.vc_pointer_reachable(C.cast(buf, C.c_void_p), 64) == 0
+    assert lib.vc_pointer_reachable(None, 16) == 0
+    assert lib.vc_pointer_reachable(C.cast(buf, C.c_void_p), 0) == 0

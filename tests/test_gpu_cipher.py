@@ -436,3 +436,40 @@ def test_encrypt_with_precomputed_hashes_matches():
     Cb = b.encrypt_hashed(frames, H)
     assert torch.equal(H, Ha) and torch.equal(Cb, Ca)
     a.close(); b.close()
+
+
+def test_hash_buffers_in_pinned_host_memory():
+    """Hash buffers may be pinned host memory (hipHostMalloc, torch's
+    pin_memory): the kernels write H there when encrypting and read it when
+    decrypting.  Pageable host memory is refused by the library before
+    anything is enqueued (checked only after vc_pointer_reachable has
+    classified it, so no kernel ever sees it)."""
+    import ctypes as C
+    dev = require_gpu()
+    Vm = V()
+    kb = key_bytes(7)
+    video = SynthVideo(64, 48, seed=2300).frames(4)
+    frames = to_dev(video, dev)
+    pinned = torch.zeros((4, 32), dtype=torch.uint8, pin_memory=True)
+    pageable = torch.zeros((4, 32), dtype=torch.uint8)
+    on_dev = torch.zeros((4, 32), dtype=torch.uint8, device=dev)
+    assert Vm.vc_pointer_reachable(pinned) and Vm.vc_pointer_reachable(on_dev) and Vm.vc_pointer_reachable(frames)
+    assert not Vm.vc_pointer_reachable(pageable)
+    c = Vm.Cipher.from_bytes(kb, -1.0, 8)
+    fr = list(frames)
+    out = torch.empty_like(frames)
+    rc = Vm.lib.encrypt_frames(C.c_void_p(c.ctx), 4, Vm._ptrs(fr), Vm._shapes(fr, [0] * 4, [0, 1, 2, 3]),
+                               C.c_void_p(pageable.data_ptr()), Vm._ptrs(list(out)), None)
+    assert rc == Vm.VC_EINVAL
+    C1, H1 = c.encrypt(frames, hashes=pinned)
+    torch.cuda.synchronize()
+    Cs, Hs, _ = oracle_stream(kb, -1.0, 8, list(video))
+    for t in range(4):
+        assert pinned[t].numpy().tobytes() == Hs[t], t
+        assert np.array_equal(to_np(C1[t]), Cs[t]), t
+    d = Vm.Cipher.from_bytes(kb, -1.0, 8)
+    Q = d.decrypt(C1, pinned)
+    torch.cuda.synchronize()
+    assert np.array_equal(to_np(Q), video)
+    assert c.status() == 0 and d.status() == 0
+    c.close(); d.close()
