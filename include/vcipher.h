@@ -92,11 +92,16 @@ uint32_t vc_protocol_version(void);
 /* Static description of a status code. Never NULL. */
 const char *vc_strerror(int status);
 
-/* Derive x0..w0 from 32 key bytes: bytes 8k..8k+7 give variable k, integer
- * part = (big-endian u16 of the first two bytes) mod 32, fraction = the
- * big-endian u48 of the next six bytes times 2^-48 (exact).  gamma and n are
- * copied.  Host only.  VC_EINVAL on NULL pointers, gamma outside
- * [-1.52, -0.06] or n outside [1, 1024]. */
+/* Derive x0..w0 from 32 key bytes.  The paper's key is the user inputs x0,
+ * y0, z0, w0 and gamma (Sec. II-A, the inputs of Alg. 1) and gives no byte
+ * encoding; this is the library's reading (protocol version 1), which
+ * takes the key bytes the way Sec. II-A's reconstruction takes the 32 hash
+ * bytes: bytes 8k..8k+7 give variable k, integer part = (big-endian u16 of
+ * the first two bytes) mod 32 (the upper bound u of Sec. II-A), fraction =
+ * the big-endian u48 of the next six bytes times 2^-48 (exact).  gamma and n
+ * are copied.  Host only.  VC_EINVAL on NULL pointers, gamma outside
+ * [-1.52, -0.06] (the hyperchaotic range of Sec. II-A) or n outside
+ * [1, 1024]. */
 int vc_key_from_bytes(const uint8_t key32[32], double gamma, uint32_t n, vc_key *out);
 
 /* Create a context on the current HIP device.  max_streams >= 1 chains are
