@@ -429,7 +429,10 @@ typedef struct {
     double launched;   /* pump time of the request's first launch */
     double done;       /* pump time at which its batch was seen complete */
     int32_t hashed;    /* went through a hash batch first */
-    int32_t status;    /* VC_OK */
+    int32_t status;    /* VC_OK; the status of a batch launch that failed; or
+                          VC_EORDER, not launched: an earlier frame of the
+                          same stream failed (the stream stays broken until
+                          its chain is restarted: vc_server_reset) */
 } vc_completion;
 
 typedef struct {
@@ -451,7 +454,8 @@ typedef struct {
  * launch(user, kind, count, tags) for every batch it forms (kind:
  * VC_REQ_ENCRYPT, VC_REQ_DECRYPT or VC_BATCH_HASH; returns a handle >= 0 or a
  * negative status) and returns the number launched (or the first negative
- * status).  vc_sched_poll returns completions in completion order.  Not
+ * status: that batch's requests complete with it, and later frames of their
+ * streams complete with VC_EORDER without being launched).  vc_sched_poll returns completions in completion order.  Not
  * thread-safe. */
 typedef struct vc_sched vc_sched;
 typedef int64_t (*vc_launch_fn)(void *user, int kind, size_t count, const uint64_t *tags);

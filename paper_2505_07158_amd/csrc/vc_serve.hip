@@ -30,6 +30,7 @@
 #include <memory>
 #include <mutex>
 #include <new>
+#include <set>
 #include <thread>
 #include <tuple>
 #include <vector>
@@ -45,6 +46,7 @@ struct Req {
     bool admitted = false;  // holds its footprint (from its first launch until done)
     bool hashed = false;    // encrypt request whose hash batch has completed
     double launched = NAN, done = NAN;
+    int status = VC_OK;     // a failed launch's status, or VC_EORDER behind one
 };
 
 struct Flight {
@@ -85,6 +87,7 @@ public:
         if (rc < 0) return rc;
         int launched = 0;
         for (int kind : {KIND_ENC, KIND_DEC, KIND_HASH}) {
+            drop_broken(kind, now);
             while (!pending[kind].empty()) {
                 std::vector<Req *> batch = form_batch(kind);
                 if (batch.empty()) break;
@@ -100,7 +103,10 @@ public:
                     if (kind != KIND_HASH) next_seq[key] = r->r.seq + 1;
                 }
                 const int64_t h = be.launch(kind, batch);
-                if (h < 0) return static_cast<int>(h);
+                if (h < 0) {
+                    fail(batch, now, static_cast<int>(h));
+                    return static_cast<int>(h);
+                }
                 inflight.push_back(Flight{kind, batch[0]->r.cls, h, std::move(batch)});
                 ++batches_launched;
                 ++launched;
@@ -114,7 +120,7 @@ public:
         while (k < max && !completed.empty()) {
             Req *r = completed.front();
             completed.pop_front();
-            out[k++] = vc_completion{r->r.tag, r->launched, r->done, r->hashed ? 1 : 0, 0};
+            out[k++] = vc_completion{r->r.tag, r->launched, r->done, r->hashed ? 1 : 0, r->status};
             forget(r);
         }
         return k;
@@ -130,6 +136,7 @@ public:
         next_seq.clear();
         next_admit.clear();
         stream_inflight.clear();
+        broken.clear();
     }
 
     void stats(vc_sched_stats *s) const {
@@ -152,6 +159,41 @@ private:
     uint64_t inflight_bytes = 0, batches_launched = 0;
     std::map<Key, uint64_t> next_seq, next_admit;  // next frame to launch / to admit per (kind, stream)
     std::map<Key, uint32_t> stream_inflight;
+    // Streams whose frame failed to launch: the library's chain did not
+    // advance past it, so their later frames would fail its order check (and
+    // take other streams' frames in the same batch with them); they complete
+    // with VC_EORDER without launching until the streams are restarted.
+    std::set<Key> broken;
+
+    // Completes a request that will not run (or ran no further).
+    void give_up(Req *r, double now, int status) {
+        const Key key{r->r.kind, r->r.stream};
+        if (r->admitted) {
+            inflight_bytes -= r->r.nbytes;
+            stream_inflight[key] -= 1;
+            r->admitted = false;
+        }
+        r->done = now;
+        r->status = status;
+        completed.push_back(r);
+    }
+
+    void fail(const std::vector<Req *> &batch, double now, int status) {
+        for (Req *r : batch) {
+            broken.insert(Key{r->r.kind, r->r.stream});
+            give_up(r, now, status);
+        }
+    }
+
+    void drop_broken(int kind, double now) {
+        if (broken.empty()) return;
+        std::deque<Req *> keep;
+        for (Req *r : pending[kind]) {
+            if (broken.count(Key{r->r.kind, r->r.stream})) give_up(r, now, VC_EORDER);
+            else keep.push_back(r);
+        }
+        pending[kind] = std::move(keep);
+    }
 
     void forget(Req *r) {
         for (auto it = owned.begin(); it != owned.end(); ++it)

@@ -53,6 +53,7 @@ class Request:
     launched: float = float("nan")
     done: float = float("nan")
     hashed: bool = False          # "enc" with hash_first: went through a hash batch
+    status: int = 0               # VC_OK, a failed launch's status, or VC_EORDER behind one
 
     @property
     def latency(self) -> float:
@@ -144,10 +145,7 @@ class Scheduler:
         Returns the number of batches launched."""
         self._now = self.clock()
         n = V.lib.vc_sched_pump(C.c_void_p(self._h), self._now, self._launch_cb, self._query_cb, None)
-        if self._error is not None:
-            err, self._error = self._error, None
-            raise err[1].with_traceback(err[2])
-        V._check(min(n, 0), "vc_sched_pump")
+        # completions first, also those of a batch whose launch just failed
         buf = (V.VcCompletion * 64)()
         while True:
             got = V.lib.vc_sched_poll(C.c_void_p(self._h), buf, 64)
@@ -155,9 +153,14 @@ class Scheduler:
                 r = self._reqs.pop(buf[i].tag)
                 r.done = buf[i].done
                 r.hashed = bool(buf[i].hashed)
+                r.status = int(buf[i].status)
                 self.completed.append(r)
             if got < 64:
                 break
+        if self._error is not None:
+            err, self._error = self._error, None
+            raise err[1].with_traceback(err[2])
+        V._check(min(n, 0), "vc_sched_pump")
         return n
 
     def idle(self) -> bool:

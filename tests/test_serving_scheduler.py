@@ -226,3 +226,38 @@ def test_hash_first_random_arrivals(seed):
         for st, q in items:
             assert q == nxt.get((kind, st), 0)
             nxt[(kind, st)] = q + 1
+
+
+def test_failed_launch_completes_its_requests_and_breaks_only_their_streams():
+    """A batch whose launch fails completes its requests with the failure's
+    status and releases their budget; later frames of those streams complete
+    with VC_EORDER without launching (the library's chain never advanced
+    past the failed frame); other streams go on."""
+    from paper_2505_07158_amd import vcipher as V
+    be = FakeBackend()
+    fail_streams = {1}
+
+    def launch(kind, reqs):
+        if any(r.stream in fail_streams for r in reqs):
+            raise RuntimeError("launch failed")
+        return be.launch(kind, reqs)
+
+    s = Scheduler(launch, hbm_budget=1000, max_batch=1, max_inflight=4)
+    s.submit(req(1, 0))
+    with pytest.raises(RuntimeError):
+        s.pump()
+    failed = [r for r in s.completed if r.stream == 1]
+    assert [(r.seq, r.status) for r in failed] == [(0, V.VC_EDEVICE)]
+    assert s.inflight_bytes == 0
+    fail_streams.clear()     # the backend recovers; stream 1 stays broken
+    for q in range(3):
+        s.submit(req(0, q))
+        s.submit(req(1, q + 1))
+    while not s.idle():
+        s.pump()
+        be.finish_all()
+    by = {(r.stream, r.seq): r.status for r in s.completed}
+    assert all(by[(0, q)] == 0 for q in range(3))
+    assert all(by[(1, q)] == V.VC_EORDER for q in range(1, 4))
+    assert all(all(st != 1 for st, _ in b) for _, b, _ in be.launched)   # stream 1 never launched again
+    assert s.inflight_bytes == 0 and s.inflight == []
