@@ -25,6 +25,7 @@
 #include <chrono>
 #include <cmath>
 #include <deque>
+#include <iterator>
 #include <list>
 #include <map>
 #include <memory>
@@ -47,6 +48,7 @@ struct Req {
     bool hashed = false;    // encrypt request whose hash batch has completed
     double launched = NAN, done = NAN;
     int status = VC_OK;     // a failed launch's status, or VC_EORDER behind one
+    std::list<std::unique_ptr<Req>>::iterator self;  // its entry in Scheduler::owned
 };
 
 struct Flight {
@@ -77,6 +79,7 @@ public:
     void submit(std::unique_ptr<Req> q) {
         Req *r = q.get();
         owned.push_back(std::move(q));
+        r->self = std::prev(owned.end());
         pending[cfg.hash_first && r->r.kind == KIND_ENC ? KIND_HASH : r->r.kind].push_back(r);
     }
 
@@ -195,13 +198,7 @@ private:
         pending[kind] = std::move(keep);
     }
 
-    void forget(Req *r) {
-        for (auto it = owned.begin(); it != owned.end(); ++it)
-            if (it->get() == r) {
-                owned.erase(it);
-                return;
-            }
-    }
+    void forget(Req *r) { owned.erase(r->self); }
 
     uint32_t inflight_of(int kind, uint64_t cls) const {
         uint32_t n = 0;
