@@ -1,0 +1,32 @@
+"""The C ABI used from plain C (tests/c_abi/roundtrip.c): hipMalloc'ed
+buffers, encrypt_frames / decrypt_frames of two streams of different shapes
+in one call, every byte, hash and chain state equal to the oracle's, and a
+pageable hash buffer refused before anything is enqueued."""
+import importlib.util
+import os
+import subprocess
+
+import pytest
+
+from gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def driver() -> str:
+    path = os.path.join(HERE, "c_abi", "roundtrip")
+    if not os.path.exists(path):
+        spec = importlib.util.spec_from_file_location("build_driver", os.path.join(HERE, "c_abi", "build_driver.py"))
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+        path = mod.build()
+    return path
+
+
+def test_c_program_round_trip_matches_oracle():
+    require_gpu()
+    r = subprocess.run([driver()], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert "roundtrip ok" in r.stdout
