@@ -145,3 +145,45 @@ def test_native_trace_replay():
         check([bufs[i] for i in order], vids, dec_in, kb, gamma, n, alone)
         srv.reset()
     srv.close()
+
+
+def test_server_rejects_bad_requests_before_launching():
+    """vc_server's documented errors: a shape that is not one of its classes,
+    a stream out of range and a pageable hash buffer are refused at submit
+    (VC_EINVAL), a trace whose arrivals are not sorted is refused, and a
+    reset while requests are pending is VC_EBUSY.  None of them launches
+    anything; the server then still serves a valid request."""
+    dev = require_gpu()
+    from paper_2505_07158_amd import vcipher as V
+    from paper_2505_07158_amd.serving import Server
+    kb = key_bytes(22)
+    srv = Server(kb, -1.0, 8, [(64, 48)], max_streams=2, hbm_budget=1 << 28, scratch_bytes=64 << 20)
+    f = torch.zeros((48, 64, 3), dtype=torch.uint8, device=dev)
+    wrong = torch.zeros((40, 64, 3), dtype=torch.uint8, device=dev)
+    out = torch.empty_like(f)
+    h = torch.zeros(32, dtype=torch.uint8, device=dev)
+    pageable = torch.zeros(32, dtype=torch.uint8)
+    assert not V.vc_pointer_reachable(pageable)
+    for r in (Server.request(0, "enc", 0, 0, wrong, torch.empty_like(wrong), h),   # not a class
+              Server.request(1, "enc", 2, 0, f, out, h),                           # stream out of range
+              Server.request(2, "enc", 0, 0, f, out, pageable)):                   # hash buffer not reachable
+        with pytest.raises(V.VcError) as e:
+            srv.submit(r)
+        assert e.value.status == V.VC_EINVAL
+    a, b = Server.request(3, "enc", 0, 0, f, out, h, arrival=0.5), Server.request(4, "enc", 0, 1, f, out, h)
+    with pytest.raises(V.VcError) as e:
+        srv.run_trace([a, b])        # arrivals 0.5 then 0.0
+    assert e.value.status == V.VC_EINVAL
+    srv.submit(Server.request(5, "enc", 0, 0, f, out, h))
+    with pytest.raises(V.VcError) as e:
+        srv.reset()                  # one request pending
+    assert e.value.status == V.VC_EBUSY
+    done = []
+    while not srv.idle():
+        srv.pump()
+        done += srv.poll()
+    torch.cuda.synchronize()
+    assert [c.tag for c in done] == [5] and done[0].status == 0 and srv.status() == 0
+    ref_c, ref_h, _ = oracle.encrypt_stream(oracle.key_from_bytes(kb), -1.0, 8, [to_np(f)])
+    assert np.array_equal(to_np(out), ref_c[0]) and to_np(h).tobytes() == ref_h[0]
+    srv.close()
