@@ -567,6 +567,28 @@ def batched_run(args, steps: int, warmup: int) -> dict:
         b2.close()
     eg.close(); dg.close()
 
+    # cpu_baseline of this workload: the oracle on this host, one core, one
+    # frame of each shape (encrypt + decrypt, from the key), checked against
+    # the GPU's bytes for it
+    import oracle
+    cpu = {}
+    cpu_s = 0.0
+    base = oracle.key_from_bytes(kb)
+    for s_ in (0, 16, 32):
+        w, h = shapes[s_]
+        P = pool[s_][0].cpu().numpy()
+        c1 = V.Cipher.from_bytes(kb, gamma, n)
+        Cg, Hg = c1.encrypt(pool[s_][0][None])
+        torch.cuda.synchronize()
+        c1.close()
+        t_c = time.perf_counter()
+        Cr, Hr, _ = oracle.encrypt_frame(base, gamma, n, P)
+        Pr = oracle.decrypt_frame(base, gamma, n, Cr, Hr)[0]
+        ms = 1000.0 * (time.perf_counter() - t_c)
+        cpu_s += ms / 1000.0
+        cpu[f"{w}x{h}"] = {"ms_per_frame": round(ms, 1),
+                           "equals_gpu": bool(np.array_equal(Cg[0].cpu().numpy(), Cr) and Hg[0].cpu().numpy().tobytes() == Hr
+                                              and np.array_equal(Pr, P))}
     line = {"metric": "batched uneven shapes: frames/s (encrypt + decrypt)", "value": round(NF * steps / el, 1),
             "unit": "frames/s", "n_gpus": 1, "steps": steps, "warmup": warmup,
             "ms_per_step": round(1000 * el / steps, 3), "higher_is_better": True, "dtype": "u8",
@@ -577,7 +599,10 @@ def batched_run(args, steps: int, warmup: int) -> dict:
             "speedup_vs_plain": round((NF * steps / el) / (NF / el1), 2),
             "roundtrip_ok": bool(ok and ok1), "plain_equals_batched": bool(same), "graph": graph,
             "autotuned": {"column_pass": tuned, "frames_per_workgroup": "one full-height strip of one frame",
-                          "mapping": "XCD-local (all strips of a frame on one XCD)"}}
+                          "mapping": "XCD-local (all strips of a frame on one XCD)"},
+            "cpu_baseline": {"value": round(3 / cpu_s, 3), "unit": "frames/s (encrypt + decrypt)", "cores": 1,
+                             "kind": "oracle", "sample": "one frame of each shape (640x480, 1280x720, 1920x1080), "
+                             "encrypt + decrypt from the key, single-threaded scalar C oracle", "per_shape": cpu}}
     enc.close(); dec.close(); e1.close(); d1.close()
     return line
 
@@ -1070,7 +1095,7 @@ def main():
     if b_ is not None:
         batched_leg = b_ if "error" in b_ else {k_: b_[k_] for k_ in (
             "value", "unit", "steps", "ms_per_step", "plain_per_frame", "speedup_vs_plain", "roundtrip_ok",
-            "plain_equals_batched", "graph", "autotuned") if k_ in b_}
+            "plain_equals_batched", "graph", "autotuned", "cpu_baseline") if k_ in b_}
         if "error" not in b_:
             batched_leg["workload"] = b_["config"]["workload"]
     serving_leg = None
