@@ -54,6 +54,8 @@ def parse():
     ap.add_argument("--max-batch", type=int, default=256, help="serving: frames per batch at most")
     ap.add_argument("--plain-frames", type=int, default=400, help="serving: arrivals replayed one frame per launch")
     ap.add_argument("--inflight", type=int, default=1, help="serving: batches in flight per kind and resolution")
+    ap.add_argument("--inflight-hash", type=int, default=0,
+                    help="serving: hash batches in flight per resolution (0 = --inflight)")
     ap.add_argument("--hash-first", type=int, default=1,
                     help="serving: 1 = hash each encrypt request on arrival, then chain/keystream/confusion in "
                     "stream order (encrypt_frames_hashed; the default); 0 = one encrypt_frames call per batch")
@@ -241,10 +243,11 @@ def serving_run(args, duration: float, plain_frames: int) -> dict:
             out = first[s][seq] if seq < P else outs[s][seq % R]
         return Server.request(i, streams[s]["kind"], s, seq, frame, out, hashes, arrival=ta)
 
-    def one_run(trace, max_batch, max_inflight, hash_first):
+    def one_run(trace, max_batch, max_inflight, hash_first, max_inflight_hash=0):
         srv = Server(kb, gamma, n, res_set, max_streams=S, hbm_budget=budget, max_inflight=max_inflight,
                      max_batch=max_batch, max_stream_inflight=R, hash_first=hash_first, parts=args.serve_parts,
-                     side_streams=args.serve_side, scratch_bytes=max(budget // len(res_set), 1 << 30))
+                     side_streams=args.serve_side, scratch_bytes=max(budget // len(res_set), 1 << 30),
+                     max_inflight_hash=max_inflight_hash)
         # warm-up: two frames of every stream at once (every kernel variant on
         # the device streams of each kind and resolution), then the chains
         # back to the key
@@ -311,7 +314,7 @@ def serving_run(args, duration: float, plain_frames: int) -> dict:
                 "decrypt_check_ok": bool(ok), "status_ok": bool(status_ok),
                 "host_cpu_ms_per_batch": round(1000.0 * cpu / max(batches, 1), 3)}
 
-    batched = one_run(trace, args.max_batch, args.inflight, bool(args.hash_first))
+    batched = one_run(trace, args.max_batch, args.inflight, bool(args.hash_first), args.inflight_hash)
     # The plain per-frame path cannot keep up with the offered load; it runs
     # the first --plain-frames arrivals of the same trace.
     plain = one_run(trace[:plain_frames], 1, 1, False)
@@ -323,6 +326,7 @@ def serving_run(args, duration: float, plain_frames: int) -> dict:
                                    f"{duration} s trace", "n": n, "offered_frames_per_s": round(offered, 1),
                        "hbm_budget_gb": args.hbm_budget_gb, "max_batch": args.max_batch,
                        "inflight_batches_per_kind_and_resolution": args.inflight,
+                       "inflight_hash_batches_per_resolution": args.inflight_hash or args.inflight,
                        "batch_class": "resolution", "hash_first": bool(args.hash_first),
                        "parts": args.serve_parts, "side_streams": args.serve_side,
                        "loop": "vc_server_run_trace (native)"},

@@ -441,6 +441,10 @@ typedef struct {
     uint32_t max_batch;            /* 0 = 512 */
     uint32_t max_stream_inflight;  /* 0 = no limit */
     int32_t hash_first;
+    uint32_t max_inflight_hash;    /* hash batches per class (0 = max_inflight): they are
+                                      latency-bound and occupy few SIMDs, so a frame that
+                                      arrives while one runs need not wait for it */
+    uint32_t reserved;             /* 0 */
 } vc_sched_config;
 
 typedef struct {
@@ -473,7 +477,8 @@ void vc_sched_destroy(vc_sched *sched);
  * creation) a sender and a receiver context (cipher_init with this key,
  * max_streams chains, scratch_bytes of scratch, 0 = hbm_budget / nclasses
  * but at least 1 GiB; vc_set_overlap(parts, side_streams, scratch_slots)
- * when parts > 0), and per kind and class max_inflight device streams used
+ * when parts > 0), and per kind and class max_inflight (hash batches:
+ * max_inflight_hash) device streams used
  * in rotation.  A batch is one call of encrypt_frames (encrypt_frames_hashed
  * after a hash batch), decrypt_frames or vc_hash_frames, with each request's
  * own hash buffer; the key state and scratch stay resident.  The clock is

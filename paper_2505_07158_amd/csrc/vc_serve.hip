@@ -73,8 +73,12 @@ class Scheduler {
 public:
     explicit Scheduler(const vc_sched_config &c) : cfg(c) {
         if (cfg.max_inflight == 0) cfg.max_inflight = 1;
+        if (cfg.max_inflight_hash == 0) cfg.max_inflight_hash = cfg.max_inflight;
         if (cfg.max_batch == 0) cfg.max_batch = 512;
     }
+
+    // Batches of a kind allowed in flight per class.
+    uint32_t limit(int kind) const { return kind == KIND_HASH ? cfg.max_inflight_hash : cfg.max_inflight; }
 
     void submit(std::unique_ptr<Req> q) {
         Req *r = q.get();
@@ -263,7 +267,7 @@ private:
                 const bool blocked =
                     full || (ordered && r->r.seq != want) || (!batch.empty() && r->r.cls != cls) ||
                     (!r->admitted && r->r.seq != next_admit[key] + taken) ||
-                    (batch.empty() && inflight_of(kind, r->r.cls) >= cfg.max_inflight) ||
+                    (batch.empty() && inflight_of(kind, r->r.cls) >= limit(kind)) ||
                     (!r->admitted && cfg.max_stream_inflight &&
                      stream_inflight[key] + taken >= cfg.max_stream_inflight);
                 if (blocked) {
@@ -316,9 +320,11 @@ struct GpuBackend : Backend {
     uint32_t nclasses = 0;
     std::vector<std::pair<uint32_t, uint32_t>> classes;  // (w, h)
     std::vector<vc_cipher *> ctx;                        // [class][enc, dec]
-    std::vector<hipStream_t> streams;                    // [class][enc, dec, hash][slot]
+    std::vector<hipStream_t> streams;                    // [class][enc slots, dec slots, hash slots]
     std::vector<uint32_t> turn;                          // [class][enc, dec, hash]
-    uint32_t slots = 1;
+    uint32_t slots[3] = {1, 1, 1};                       // device streams per kind and class
+
+    uint32_t per_class() const { return slots[0] + slots[1] + slots[2]; }
     std::vector<hipEvent_t> events;
     std::vector<int64_t> free_events;
 
@@ -344,8 +350,10 @@ struct GpuBackend : Backend {
             shapes[i] = vc_shape{r.w, r.h, 3, r.stream, r.seq};
         }
         uint32_t &t = turn[3 * ci + kind];
-        const hipStream_t st = streams[(3 * ci + kind) * slots + t];
-        t = (t + 1) % slots;
+        uint32_t first = ci * per_class();
+        for (int k = 0; k < kind; ++k) first += slots[k];
+        const hipStream_t st = streams[first + t];
+        t = (t + 1) % slots[kind];
         vc_cipher *c = ctx[2 * ci + (kind == KIND_DEC ? 1 : 0)];
         const vc::CallKind ck = kind == KIND_HASH   ? vc::CallKind::Hash
                                 : kind == KIND_DEC  ? vc::CallKind::Decrypt
@@ -452,7 +460,10 @@ int vc_server_create(const vc_key *key, const uint32_t *classes, size_t nclasses
         return VC_EDEVICE;
     }
     be.nclasses = static_cast<uint32_t>(nclasses);
-    be.slots = cfg->sched.max_inflight ? cfg->sched.max_inflight : 1;
+    be.slots[KIND_ENC] = be.slots[KIND_DEC] = cfg->sched.max_inflight ? cfg->sched.max_inflight : 1;
+    be.slots[KIND_HASH] = !cfg->sched.hash_first       ? 0  // no hash batches
+                          : cfg->sched.max_inflight_hash ? cfg->sched.max_inflight_hash
+                                                         : be.slots[KIND_ENC];
     const uint64_t scratch = cfg->scratch_bytes ? cfg->scratch_bytes
                                                 : std::max<uint64_t>(cfg->sched.hbm_budget / nclasses, uint64_t(1) << 30);
     int rc = VC_OK;
@@ -466,7 +477,7 @@ int vc_server_create(const vc_key *key, const uint32_t *classes, size_t nclasses
                 if (cfg->parts) rc = vc_set_overlap(cx, cfg->parts, cfg->side_streams, cfg->scratch_slots ? cfg->scratch_slots : 2);
             }
         }
-        for (uint32_t k = 0; k < 3 * be.slots && rc == VC_OK; ++k) {
+        for (uint32_t k = 0; k < be.per_class() && rc == VC_OK; ++k) {
             hipStream_t st = nullptr;
             if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) rc = VC_EDEVICE;
             else be.streams.push_back(st);

@@ -19,7 +19,8 @@ times.  The scheduling rules live in the library (vc_sched, vc_server):
 * a batch is one library call over any mix of streams of one class (the
   server uses the resolution, so small frames do not wait for the serial
   SHA-256 and key schedule of large ones), launched whenever fewer than
-  ``max_inflight`` batches of its kind and class are in flight.
+  ``max_inflight`` batches of its kind and class are in flight
+  (``max_inflight_hash`` for hash batches, 0 = the same).
 
 :class:`Scheduler` drives the native core with a backend written in Python
 (the CPU tests use fake backends); :class:`Server` is the native core with
@@ -70,12 +71,12 @@ class Scheduler:
     def __init__(self, launch: Callable[[str, List[Request]], object], hbm_budget: int, max_inflight: int = 2,
                  max_batch: int = 512, clock: Callable[[], float] = time.perf_counter,
                  batch_class: Optional[Callable[[Request], object]] = None, max_stream_inflight: int = 0,
-                 hash_first: bool = False):
+                 hash_first: bool = False, max_inflight_hash: int = 0):
         self.launch = launch
         self.clock = clock
         self.batch_class = batch_class
         cfg = V.VcSchedConfig(int(hbm_budget), int(max_inflight), int(max_batch), int(max_stream_inflight),
-                              1 if hash_first else 0)
+                              1 if hash_first else 0, int(max_inflight_hash), 0)
         h = C.c_void_p()
         V._check(V.lib.vc_sched_create(C.byref(cfg), C.byref(h)), "vc_sched_create")
         self._h = h.value
@@ -194,12 +195,13 @@ class Server:
     def __init__(self, key32: bytes, gamma: float, n: int, classes: Sequence[Tuple[int, int]], max_streams: int,
                  hbm_budget: int, max_inflight: int = 1, max_batch: int = 256, max_stream_inflight: int = 0,
                  hash_first: bool = False, parts: int = 1, side_streams: int = 0, scratch_slots: int = 2,
-                 scratch_bytes: int = 0):
+                 scratch_bytes: int = 0, max_inflight_hash: int = 0):
         self.key = V.vc_key_from_bytes(key32, gamma, n)
         self.classes = [(int(w), int(h)) for w, h in classes]
         cls = (C.c_uint32 * (2 * len(self.classes)))(*[v for wh in self.classes for v in wh])
         cfg = V.VcServerConfig(V.VcSchedConfig(int(hbm_budget), int(max_inflight), int(max_batch),
-                                               int(max_stream_inflight), 1 if hash_first else 0),
+                                               int(max_stream_inflight), 1 if hash_first else 0,
+                                               int(max_inflight_hash), 0),
                                int(max_streams), int(parts), int(side_streams), int(scratch_slots), int(scratch_bytes))
         h = C.c_void_p()
         V._check(V.lib.vc_server_create(C.byref(self.key), cls, len(self.classes), C.byref(cfg), C.byref(h)),

@@ -54,7 +54,8 @@ class VcCompletion(C.Structure):
 
 class VcSchedConfig(C.Structure):
     _fields_ = [("hbm_budget", C.c_uint64), ("max_inflight", C.c_uint32), ("max_batch", C.c_uint32),
-                ("max_stream_inflight", C.c_uint32), ("hash_first", C.c_int32)]
+                ("max_stream_inflight", C.c_uint32), ("hash_first", C.c_int32), ("max_inflight_hash", C.c_uint32),
+                ("reserved", C.c_uint32)]
 
 
 class VcSchedStats(C.Structure):

@@ -261,3 +261,23 @@ def test_failed_launch_completes_its_requests_and_breaks_only_their_streams():
     assert all(by[(1, q)] == V.VC_EORDER for q in range(1, 4))
     assert all(all(st != 1 for st, _ in b) for _, b, _ in be.launched)   # stream 1 never launched again
     assert s.inflight_bytes == 0 and s.inflight == []
+
+
+def test_hash_batches_have_their_own_inflight_limit():
+    """max_inflight_hash: hash batches (latency-bound, few SIMDs) may run
+    several at once per class while the ordered stage keeps max_inflight."""
+    be = FakeBackend()
+    s = Scheduler(be.launch, hbm_budget=10**9, max_inflight=1, max_batch=1, hash_first=True, max_inflight_hash=3)
+    for k in range(5):
+        s.submit(req(k, 0))
+    s.pump()
+    assert [kind for kind, _, _ in be.launched] == ["hash"] * 3     # three hash batches, not one
+    assert len(s.inflight) == 3
+    be.finish_all()
+    s.pump()
+    kinds = [kind for kind, _, _ in be.launched[3:]]
+    assert kinds.count("enc") == 1 and kinds.count("hash") == 2   # one ordered batch; the last two hashes
+    while not s.idle():
+        be.finish_all()
+        s.pump()
+    assert len(s.completed) == 5 and all(r.hashed for r in s.completed)
