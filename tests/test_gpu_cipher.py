@@ -341,6 +341,12 @@ def test_documented_errors():
     with pytest.raises(Vm.VcError) as e:
         Vm.encrypt_frames(tiny.ctx, [t], [0], [0], H, [torch.empty_like(t)])
     assert e.value.status == Vm.VC_EINVAL
+    # a shape whose channel count is not 3 (the binding always sends 3: raw call)
+    import ctypes as C
+    sh = (Vm.VcShape * 1)(Vm.VcShape(16, 16, 2, 0, 0))
+    rc = Vm.lib.encrypt_frames(C.c_void_p(c.ctx), 1, Vm._ptrs([f]), sh, C.c_void_p(H.data_ptr()), Vm._ptrs([out]),
+                               None)
+    assert rc == Vm.VC_EINVAL
     # failed calls enqueue nothing: the stream still starts at seq 0
     Vm.encrypt_frames(c.ctx, [f], [0], [0], H, [out])
     assert c.status() == 0
