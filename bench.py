@@ -615,8 +615,8 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (streams would shard "
-              "across GPUs with no collective; see the design notes).  Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (streams would be sharded across "
+              "GPUs, each with its own chain states, with no collective).  Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
     # The batched and serving legs of the default run go first, each in a
     # child process of its own (before this process touches the GPU): the

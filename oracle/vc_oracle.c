@@ -9,8 +9,8 @@
  * benchmark's CPU-baseline leg may load it.
  *
  * Where the paper leaves a detail open, the reading used here is marked
- * [Rk] and is the protocol-v1 reading listed with its justification in the
- * design notes of this repository.
+ * [Rk] where it is applied (protocol version 1), with the passage it
+ * interprets and the choice made.
  *
  * Parity status of each part:
  *   SHA-256 and the frame hash ....... pinned (hashlib, openssl, FIPS 180-4

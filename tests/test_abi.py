@@ -124,3 +124,13 @@ def test_pointer_reachable_refuses_host_memory(lib):
     assert lib.vc_pointer_reachable(C.cast(buf, C.c_void_p), 64) == 0
     assert lib.vc_pointer_reachable(None, 16) == 0
     assert lib.vc_pointer_reachable(C.cast(buf, C.c_void_p), 0) == 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU; --gpus above 1 exits with a message (no GPU
+    is touched)."""
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode != 0 and "one GPU" in r.stderr
