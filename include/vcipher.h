@@ -485,11 +485,17 @@ void vc_sched_destroy(vc_sched *sched);
  * seconds since creation (vc_server_clock).  vc_server_run_trace replays
  * `count` requests sorted by arrival (seconds from the call), submitting each
  * when the clock reaches it and pumping until all are done, and writes
- * done[i] for reqs[i] (times relative to the call).  vc_server_reset sets
+ * done[i] for reqs[i] (times relative to the call); it checks every request
+ * (and the order of arrivals) before submitting any, and is VC_EBUSY unless
+ * the server is idle with no unpolled completion.  If a launch fails during
+ * the replay it returns that status at once: later requests are not
+ * submitted, and those already submitted complete through vc_server_poll
+ * with their index in reqs as the tag.  vc_server_reset sets
  * every chain back to the key and every stream's next frame back to seq 0
  * (VC_EBUSY unless idle).  Errors: VC_EINVAL for
- * a shape that is not one of the classes, a stream out of range or NULL
- * buffers; a failing library call is returned by pump. */
+ * a shape that is not one of the classes, a stream out of range, NULL
+ * buffers or a hash buffer that the device cannot reach
+ * (vc_pointer_reachable); a failing library call is returned by pump. */
 typedef struct vc_server vc_server;
 typedef struct {
     vc_sched_config sched;

@@ -494,18 +494,35 @@ int vc_server_create(const vc_key *key, const uint32_t *classes, size_t nclasses
 
 double vc_server_clock(const vc_server *srv) { return srv ? seconds_since(srv->t0) : 0.0; }
 
-int vc_server_submit(vc_server *srv, const vc_request *req) {
-    if (!srv || !req || (req->kind != KIND_ENC && req->kind != KIND_DEC) || !req->frame || !req->out || !req->hash ||
+}  // extern "C"
+
+namespace {
+
+// The class (index of the resolution) of a request the server can take, or
+// nclasses when it cannot: a kind other than encrypt / decrypt, a NULL
+// buffer, a stream out of range, a hash buffer the device cannot reach or a
+// shape that is not one of the classes.
+uint32_t request_class(const vc_server *srv, const vc_request *req) {
+    const uint32_t none = srv->be.nclasses;
+    if ((req->kind != KIND_ENC && req->kind != KIND_DEC) || !req->frame || !req->out || !req->hash ||
         req->stream >= srv->max_streams || !vc::reachable(req->hash, 32))
-        return VC_EINVAL;
+        return none;
+    for (uint32_t c = 0; c < srv->be.nclasses; ++c)
+        if (srv->be.classes[c].first == req->w && srv->be.classes[c].second == req->h) return c;
+    return none;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vc_server_submit(vc_server *srv, const vc_request *req) {
+    if (!srv || !req) return VC_EINVAL;
+    const uint32_t ci = request_class(srv, req);
+    if (ci == srv->be.nclasses) return VC_EINVAL;
     std::unique_ptr<Req> r(new (std::nothrow) Req());
     if (!r) return VC_ENOMEM;
     r->r = *req;
-    // the class is the index of the request's resolution
-    uint32_t ci = srv->be.nclasses;
-    for (uint32_t c = 0; c < srv->be.nclasses; ++c)
-        if (srv->be.classes[c].first == req->w && srv->be.classes[c].second == req->h) ci = c;
-    if (ci == srv->be.nclasses) return VC_EINVAL;
     r->r.cls = ci;
     if (!r->r.nbytes) r->r.nbytes = 6ull * req->w * req->h + vc_scratch_per_frame(req->w, req->h, srv->key.n);
     std::lock_guard<std::mutex> lk(srv->mu);
@@ -540,8 +557,18 @@ int vc_server_get_stats(vc_server *srv, vc_sched_stats *st) {
 
 int vc_server_run_trace(vc_server *srv, size_t count, const vc_request *reqs, vc_completion *done) {
     if (!srv || (count && (!reqs || !done))) return VC_EINVAL;
-    for (size_t i = 1; i < count; ++i)
-        if (reqs[i].arrival < reqs[i - 1].arrival) return VC_EINVAL;
+    // the whole trace is checked before anything is submitted
+    for (size_t i = 0; i < count; ++i)
+        if ((i && reqs[i].arrival < reqs[i - 1].arrival) || request_class(srv, &reqs[i]) == srv->be.nclasses)
+            return VC_EINVAL;
+    {
+        // completions are matched to reqs by index: nothing else may be
+        // pending, in flight or unpolled
+        std::lock_guard<std::mutex> lk(srv->mu);
+        vc_sched_stats st{};
+        srv->core.stats(&st);
+        if (!srv->core.idle() || st.completed_unpolled) return VC_EBUSY;
+    }
     // completions are reported in the order of reqs: the internal tag is the index
     const double base = vc_server_clock(srv);
     size_t next = 0, finished = 0;

@@ -150,9 +150,10 @@ def test_native_trace_replay():
 def test_server_rejects_bad_requests_before_launching():
     """vc_server's documented errors: a shape that is not one of its classes,
     a stream out of range and a pageable hash buffer are refused at submit
-    (VC_EINVAL), a trace whose arrivals are not sorted is refused, and a
-    reset while requests are pending is VC_EBUSY.  None of them launches
-    anything; the server then still serves a valid request."""
+    (VC_EINVAL); a trace whose arrivals are not sorted, or that holds such a
+    request anywhere, is refused whole; a reset or a trace replay while
+    requests are pending is VC_EBUSY.  None of them launches anything; the
+    server then still serves a valid request."""
     dev = require_gpu()
     from paper_2505_07158_amd import vcipher as V
     from paper_2505_07158_amd.serving import Server
@@ -174,9 +175,20 @@ def test_server_rejects_bad_requests_before_launching():
     with pytest.raises(V.VcError) as e:
         srv.run_trace([a, b])        # arrivals 0.5 then 0.0
     assert e.value.status == V.VC_EINVAL
+    # a bad request late in a trace: the whole trace is refused before the
+    # valid requests ahead of it are submitted
+    good = Server.request(6, "enc", 0, 0, f, out, h)
+    bad = Server.request(7, "enc", 0, 1, f, out, pageable, arrival=0.001)
+    with pytest.raises(V.VcError) as e:
+        srv.run_trace([good, bad])
+    assert e.value.status == V.VC_EINVAL
+    assert srv.idle() and srv.stats().batches_launched == 0 and srv.stats().pending == 0
     srv.submit(Server.request(5, "enc", 0, 0, f, out, h))
     with pytest.raises(V.VcError) as e:
         srv.reset()                  # one request pending
+    assert e.value.status == V.VC_EBUSY
+    with pytest.raises(V.VcError) as e:
+        srv.run_trace([Server.request(8, "enc", 0, 1, f, out, h)])   # the server is not idle
     assert e.value.status == V.VC_EBUSY
     done = []
     while not srv.idle():
