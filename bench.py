@@ -86,6 +86,9 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the CPU-oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stats", action="store_true", help="skip the statistics of one ciphertext batch")
+    ap.add_argument("--graph-form", choices=["staged", "pair", "both"], default="staged",
+                    help="batched: graph form (staged = hash / encrypt / decrypt of three blocks per replay, "
+                         "pair = encrypt and decrypt of two blocks per replay)")
     ap.add_argument("--batched-steps", type=int, default=8,
                     help="video workload: steps of the batched uneven-shape leg (0 = skip)")
     ap.add_argument("--serving-seconds", type=float, default=8.0,
@@ -510,65 +513,107 @@ def batched_run(args, steps: int, warmup: int) -> dict:
     assert enc.status() == 0 and dec.status() == 0
 
     # ---- the same batches as prepared batches (vc_batch_prepare), launched
-    # from HIP graphs.  Two sets of ciphertext and hash buffers; graph j
-    # holds, on two forked capture streams, the encrypt launch into set j and
-    # the decrypt launch of set 1 - j (encrypted by the previous replay), so
-    # that sender and receiver overlap as in the call path above.  Replaying
-    # graph 1, 0, 1, 0, ... after one eager encrypt into set 0 encrypts block
-    # k + 1 while block k is decrypted; every kernel is a launch from the
-    # graph (no host work per batch).
+    # from HIP graphs; every kernel is a launch from a graph (no host work
+    # per batch).
+    #  staged: three buffer sets of hashes and ciphertext; graph j holds, on
+    #    three forked capture streams, the hash batch of set j + 2, the
+    #    encrypt-from-hashes batch of set j + 1 and the decrypt batch of set
+    #    j, so replay r hashes block r + 2, encrypts block r + 1 and decrypts
+    #    block r (SHA-256 of one block overlaps the key schedule and
+    #    confusion of the next, as on the call path's alternating streams);
+    #  pair: two sets; graph j holds the whole encrypt launch into set j and,
+    #    on a forked capture stream, the decrypt launch of set 1 - j.
     eg = V.Cipher.from_bytes(kb, gamma, n, max_streams=len(shapes))
     dg = V.Cipher.from_bytes(kb, gamma, n, max_streams=len(shapes))
     for (w, h) in sorted(set(shapes)):
         for c_, dd in ((eg, False), (dg, True)):
             c_.autotune(w, h, frames=F * 16, decrypt=dd)
     gseqs = [f % F for f in range(NF)]
-    cg = [[torch.empty_like(x) for x in frames] for _ in range(2)]
     pg = [torch.empty_like(x) for x in frames]
-    hg = [torch.empty((NF, 32), dtype=torch.uint8, device=dev) for _ in range(2)]
-    eb = [V.Batch(eg.ctx, False, frames, sids, gseqs, hg[j], cg[j]) for j in range(2)]
-    db = [V.Batch(dg.ctx, True, cg[j], sids, gseqs, hg[j], pg) for j in range(2)]
-    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
-    eb[0].launch(sa)                         # eager: block 0 (frames 0..7 of every stream) into set 0
-    torch.cuda.synchronize()
-    graph_same = all(torch.equal(cg[0][i], c0[i]) for i in range(NF)) and torch.equal(hg[0], hbuf[0])
-    graphs = []
-    for j in range(2):
-        g = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(g, stream=sa):
-            fork = torch.cuda.Event()
-            fork.record(sa)
-            sb.wait_event(fork)
-            eb[j].launch(sa)
-            db[1 - j].launch(sb)
+
+    def fork_join(s0, launches):
+        """Captures launches[i] on stream i (stream 0 = the capture stream)."""
+        fork = torch.cuda.Event()
+        fork.record(s0[0])
+        for st in s0[1:]:
+            st.wait_event(fork)
+        for st, fn in zip(s0, launches):
+            fn(st)
+        for st in s0[1:]:
             join = torch.cuda.Event()
-            join.record(sb)
-            sa.wait_event(join)
-        graphs.append(g)
-    graph_rt = True
-    r = 0
-    for _ in range(warmup):
-        graphs[(r + 1) % 2].replay()         # encrypt block r + 1, decrypt block r
-        r += 1
-    torch.cuda.synchronize()
-    graph_rt = graph_rt and all(torch.equal(pg[i], frames[i]) for i in range(NF))
-    t2 = time.perf_counter()
-    for _ in range(steps):
-        graphs[(r + 1) % 2].replay()
-        r += 1
-    torch.cuda.synchronize()
-    el2 = time.perf_counter() - t2
-    graph_rt = graph_rt and all(torch.equal(pg[i], frames[i]) for i in range(NF))
-    assert eg.status() == 0 and dg.status() == 0
-    graph = {"value": round(NF * steps / el2, 1), "unit": "frames/s", "steps": steps,
-             "ms_per_step": round(1000 * el2 / steps, 3), "first_launch_equals_call_path": bool(graph_same),
-             "roundtrip_ok": bool(graph_rt), "speedup_vs_plain": round((NF * steps / el2) / (NF / el1), 2),
-             "mode": "vc_batch_prepare once per direction and buffer set; two HIP graphs, each an encrypt batch "
-                     "launch and, on a forked capture stream, the decrypt launch of the previous block; a replay "
-                     "encrypts the next 8 frames of every stream and decrypts the 8 before"}
-    del graphs
-    for b2 in eb + db:
-        b2.close()
+            join.record(st)
+            s0[0].wait_event(join)
+
+    def graph_leg(form):
+        # every chain back to the key: each form starts at block 0
+        torch.cuda.synchronize()
+        for s_ in range(len(shapes)):
+            eg.reset(s_)
+            dg.reset(s_)
+        NSET = 3 if form == "staged" else 2
+        cg = [[torch.empty_like(x) for x in frames] for _ in range(NSET)]
+        hg = [torch.empty((NF, 32), dtype=torch.uint8, device=dev) for _ in range(NSET)]
+        db = [V.Batch(dg.ctx, "decrypt", cg[j], sids, gseqs, hg[j], pg) for j in range(NSET)]
+        if form == "staged":
+            hb = [V.Batch(eg.ctx, "hash", frames, sids, gseqs, hg[j], None) for j in range(NSET)]
+            eb = [V.Batch(eg.ctx, "encrypt_hashed", frames, sids, gseqs, hg[j], cg[j]) for j in range(NSET)]
+        else:
+            hb = []
+            eb = [V.Batch(eg.ctx, "encrypt", frames, sids, gseqs, hg[j], cg[j]) for j in range(NSET)]
+        st = [torch.cuda.Stream() for _ in range(3 if form == "staged" else 2)]
+        # eager prologue: block 0 encrypted into set 0 (staged: and block 1 hashed)
+        if form == "staged":
+            hb[0].launch(st[0])
+            eb[0].launch(st[0])
+            hb[1].launch(st[0])
+        else:
+            eb[0].launch(st[0])
+        torch.cuda.synchronize()
+        same = all(torch.equal(cg[0][i], c0[i]) for i in range(NF)) and torch.equal(hg[0], hbuf[0])
+        graphs = []
+        for j in range(NSET):
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g, stream=st[0]):
+                if form == "staged":       # graph j is replay r with r % 3 == j
+                    fork_join(st, [hb[(j + 2) % 3].launch, eb[(j + 1) % 3].launch, db[j].launch])
+                else:                      # graph j encrypts into set j, decrypts set 1 - j
+                    fork_join(st, [eb[j].launch, db[1 - j].launch])
+            graphs.append(g)
+        pick = (lambda r: graphs[r % 3]) if form == "staged" else (lambda r: graphs[(r + 1) % 2])
+        rt = True
+        r = 0
+        for _ in range(warmup):
+            pick(r).replay()
+            r += 1
+        torch.cuda.synchronize()
+        rt = rt and all(torch.equal(pg[i], frames[i]) for i in range(NF))
+        t2 = time.perf_counter()
+        for _ in range(steps):
+            pick(r).replay()
+            r += 1
+        torch.cuda.synchronize()
+        el2 = time.perf_counter() - t2
+        rt = rt and all(torch.equal(pg[i], frames[i]) for i in range(NF))
+        assert eg.status() == 0 and dg.status() == 0
+        del graphs
+        for b2 in hb + eb + db:
+            b2.close()
+        mode = ("vc_batch_prepare once per stage and buffer set; three HIP graphs over three sets, each with a hash "
+                "batch, an encrypt-from-hashes batch and a decrypt batch on forked capture streams; replay r hashes "
+                "block r + 2, encrypts block r + 1 and decrypts block r (8 frames of every stream per block)"
+                if form == "staged" else
+                "vc_batch_prepare once per direction and buffer set; two HIP graphs, each an encrypt batch launch "
+                "and, on a forked capture stream, the decrypt launch of the previous block; a replay encrypts the "
+                "next 8 frames of every stream and decrypts the 8 before")
+        return {"value": round(NF * steps / el2, 1), "unit": "frames/s", "steps": steps,
+                "ms_per_step": round(1000 * el2 / steps, 3), "first_launch_equals_call_path": bool(same),
+                "roundtrip_ok": bool(rt), "speedup_vs_plain": round((NF * steps / el2) / (NF / el1), 2),
+                "form": form, "mode": mode}
+
+    forms = ["staged", "pair"] if args.graph_form == "both" else [args.graph_form]
+    graph = graph_leg(forms[0])
+    if len(forms) > 1:
+        graph["other_form"] = graph_leg(forms[1])
     eg.close(); dg.close()
 
     # cpu_baseline of this workload: the oracle on this host, one core, one

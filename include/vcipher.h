@@ -56,7 +56,8 @@ typedef enum {
     VC_EORDER = -4,      /* frames of a stream out of sequence               */
     VC_ENONFINITE = -5,  /* an LHCS trajectory left the finite range
                             (reported by cipher_status)                      */
-    VC_EBUSY = -6        /* reserved                                         */
+    VC_EBUSY = -6        /* the serving loop has work pending (reset,
+                            trace replay)                                   */
 } vc_status;
 
 /* The user key of Alg. 1 (Require): initial conditions x0, y0, z0, w0 and
@@ -377,13 +378,25 @@ int vc_frame_diff(size_t count, const uint8_t *const *a, const uint8_t *const *b
  * caller orders a context's batch launches with its other calls (they share
  * its chain states), keeps every buffer alive while the batch exists, and
  * must not prepare a batch while another call of the context may be
- * running.  decrypt = 0: frames are plaintext, hashes (count*32 bytes)
- * receive H; decrypt = 1: frames are ciphertext, hashes hold the sender's
- * H.  Tiling (autotuned or fixed) is taken at prepare time.  Kernel
- * profiling does not time batch launches.  Errors: as encrypt_frames, plus
- * VC_ENOMEM if the batch's scratch cannot be allocated. */
+ * running.  `mode`:
+ *   VC_PREP_ENCRYPT: frames are plaintext, hashes (count*32 bytes, device or
+ *     pinned host memory) receive H, out the ciphertext (Sec. II, Alg. 1);
+ *   VC_PREP_DECRYPT: frames are ciphertext, hashes hold the sender's H;
+ *   VC_PREP_HASH: only the frame hash H of each frame (Sec. II-A: the
+ *     sub-frame SHA-256 digests xored), into hashes; out may be NULL, the
+ *     streams and seqs are not used, no chain advances and the batch holds
+ *     no scratch.  H depends on the frame alone, so a caller may hash block
+ *     k+1 while block k is encrypted;
+ *   VC_PREP_ENCRYPT_HASHED: as VC_PREP_ENCRYPT, with hashes already holding
+ *     H of these frames (from a VC_PREP_HASH launch or vc_hash_frames);
+ *     the frames are not hashed again.
+ * Other values are VC_EINVAL.  Tiling (autotuned or fixed) is taken at
+ * prepare time.  Kernel profiling does not time batch launches.  Errors: as
+ * encrypt_frames, plus VC_ENOMEM if the batch's scratch cannot be
+ * allocated. */
 typedef struct vc_batch vc_batch;
-int vc_batch_prepare(vc_cipher *ctx, int decrypt, size_t count, const uint8_t *const *frames,
+enum { VC_PREP_ENCRYPT = 0, VC_PREP_DECRYPT = 1, VC_PREP_HASH = 2, VC_PREP_ENCRYPT_HASHED = 3 };
+int vc_batch_prepare(vc_cipher *ctx, int mode, size_t count, const uint8_t *const *frames,
                      const vc_shape *shapes, uint8_t *hashes, uint8_t *const *out, vc_batch **batch);
 int vc_batch_launch(vc_batch *batch, void *stream);
 /* Frees the batch (synchronises its device first).  NULL is a no-op. */

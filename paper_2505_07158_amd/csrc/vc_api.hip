@@ -1397,6 +1397,7 @@ int vc_autotune(vc_cipher *ctx, int decrypt, uint32_t w, uint32_t h, uint32_t fr
 
 struct vc_batch {
     vc_cipher *ctx = nullptr;
+    int mode = VC_PREP_ENCRYPT;
     int decrypt = 0;
     bool two_pass = true;
     uint32_t count = 0;
@@ -1420,16 +1421,21 @@ void batch_free(vc_batch *b) {
 
 extern "C" {
 
-int vc_batch_prepare(vc_cipher *ctx, int decrypt, size_t count, const uint8_t *const *frames, const vc_shape *shapes,
+int vc_batch_prepare(vc_cipher *ctx, int mode, size_t count, const uint8_t *const *frames, const vc_shape *shapes,
                      uint8_t *hashes, uint8_t *const *out, vc_batch **batch) {
     if (batch) *batch = nullptr;
-    if (!ctx || !batch || count == 0 || count > 0xFFFFFFFFull || !frames || !shapes || !hashes || !out)
+    const bool hash_only = mode == VC_PREP_HASH;
+    if (mode != VC_PREP_ENCRYPT && mode != VC_PREP_DECRYPT && !hash_only && mode != VC_PREP_ENCRYPT_HASHED)
+        return VC_EINVAL;
+    if (!ctx || !batch || count == 0 || count > 0xFFFFFFFFull || !frames || !shapes || !hashes ||
+        (!out && !hash_only))
         return VC_EINVAL;
     std::lock_guard<std::mutex> lk(ctx->mu);
     DeviceGuard g(ctx->device);
     if (!g.ok) return VC_EDEVICE;
-    const int dec = decrypt ? 1 : 0;
-    const bool two_pass = ctx->passes == 2;
+    const int dec = mode == VC_PREP_DECRYPT ? 1 : 0;
+    // a hash batch runs only the frame hashes: no chain, no scratch
+    const bool two_pass = ctx->passes == 2 && !hash_only;
     const uint32_t n = ctx->key.n;
     std::map<uint32_t, uint64_t> last_seq;
     uint64_t need = 0;
@@ -1437,29 +1443,38 @@ int vc_batch_prepare(vc_cipher *ctx, int decrypt, size_t count, const uint8_t *c
         const vc_shape &s = shapes[f];
         const int rc = check_shape(ctx, s, dec, true);
         if (rc) return rc;
+        if (!frames[f]) return VC_EINVAL;
+        if (hash_only) continue;
         const uint64_t L = frame_bytes(s);
-        if (!frames[f] || !out[f] || overlaps(frames[f], L, out[f], L)) return VC_EINVAL;
+        if (!out[f] || overlaps(frames[f], L, out[f], L)) return VC_EINVAL;
         if (s.stream >= ctx->max_streams) return VC_EINVAL;
         auto it = last_seq.find(s.stream);
         if (it != last_seq.end() && s.seq <= it->second) return VC_EORDER;
         last_seq[s.stream] = s.seq;
         need += scratch_need(s, n, true, two_pass);
     }
+    // the kernels read and write the hash buffer in place
+    if (!reachable(hashes, 32 * count)) return VC_EINVAL;
     vc_batch *b = new (std::nothrow) vc_batch();
     if (!b) return VC_ENOMEM;
     b->ctx = ctx;
+    b->mode = mode;
     b->decrypt = dec;
     b->two_pass = two_pass;
     b->count = static_cast<uint32_t>(count);
-    for (size_t f = 0; f < count; ++f) b->frames_per_stream[shapes[f].stream] += 1;
+    if (!hash_only)
+        for (size_t f = 0; f < count; ++f) b->frames_per_stream[shapes[f].stream] += 1;
     CallArgs a{};
-    a.op = dec ? Op::Decrypt : Op::Encrypt;
+    a.op = mode == VC_PREP_DECRYPT         ? Op::Decrypt
+           : mode == VC_PREP_HASH          ? Op::Hash
+           : mode == VC_PREP_ENCRYPT_HASHED ? Op::EncryptHashed
+                                            : Op::Encrypt;
     a.count = count;
     a.in = frames;
     a.shapes = shapes;
-    if (dec) a.hashes = hashes;
+    if (mode == VC_PREP_DECRYPT || mode == VC_PREP_ENCRYPT_HASHED) a.hashes = hashes;
     else a.hashes_out = hashes;
-    a.out = out;
+    a.out = hash_only ? nullptr : out;
     // descriptors first (at most one run and one chain record per frame),
     // then one span of scratch for every frame
     const size_t desc_max = align_up(sizeof(FrameDesc) * count, 256) + align_up(sizeof(StreamRun) * count, 256) +
@@ -1470,13 +1485,14 @@ int vc_batch_prepare(vc_cipher *ctx, int decrypt, size_t count, const uint8_t *c
         return map_err(e);
     }
     Plan P;
-    build_plan(ctx, a, true, two_pass, true, true, dec, need, 1, [&](uint32_t) { return b->d_mem + desc_max; }, P);
+    build_plan(ctx, a, !hash_only, two_pass, !hash_only, !hash_only, dec, need, 1,
+               [&](uint32_t) { return b->d_mem + desc_max; }, P);
     const size_t desc_bytes = align_up(sizeof(FrameDesc) * count, 256);
     const size_t runs_bytes = align_up(sizeof(StreamRun) * count, 256);
     e = hipMemcpy(b->d_mem, P.desc.data(), sizeof(FrameDesc) * count, hipMemcpyHostToDevice);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !P.runs.empty())
         e = hipMemcpy(b->d_mem + desc_bytes, P.runs.data(), sizeof(StreamRun) * P.runs.size(), hipMemcpyHostToDevice);
-    if (e == hipSuccess)
+    if (e == hipSuccess && !P.order.empty())
         e = hipMemcpy(b->d_mem + desc_bytes + runs_bytes, P.order.data(), sizeof(ChainRec) * P.order.size(),
                       hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -1486,7 +1502,7 @@ int vc_batch_prepare(vc_cipher *ctx, int decrypt, size_t count, const uint8_t *c
     b->d_desc = reinterpret_cast<const FrameDesc *>(b->d_mem);
     b->d_runs = reinterpret_cast<const StreamRun *>(b->d_mem + desc_bytes);
     b->d_order = reinterpret_cast<const ChainRec *>(b->d_mem + desc_bytes + runs_bytes);
-    b->chunks = P.chunks;
+    if (!hash_only) b->chunks = P.chunks;
     for (const Chunk &ch : b->chunks) {
         std::vector<ConfuseTuning> t;
         for (const Group &gr : ch.groups) t.push_back(choose_tiling(ctx, dec, gr.w, gr.h));
@@ -1505,7 +1521,7 @@ int vc_batch_launch(vc_batch *b, void *stream) {
     const hipStream_t s = static_cast<hipStream_t>(stream);
     const uint32_t n = ctx->key.n;
     hipError_t e = hipSuccess;
-    if (!b->decrypt) e = launch_sha256_subframes(b->d_desc, b->count, n, s);
+    if (b->mode == VC_PREP_ENCRYPT || b->mode == VC_PREP_HASH) e = launch_sha256_subframes(b->d_desc, b->count, n, s);
     const hipStream_t ws = s;
     for (size_t ci = 0; ci < b->chunks.size() && e == hipSuccess; ++ci) {
         const Chunk &ch = b->chunks[ci];

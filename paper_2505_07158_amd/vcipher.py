@@ -346,22 +346,31 @@ def vc_debug_keysched(ctx: int, shapes_hw: Sequence[Tuple[int, int]], streams: S
     _check(rc, "vc_debug_keysched")
 
 
+VC_PREP_ENCRYPT, VC_PREP_DECRYPT, VC_PREP_HASH, VC_PREP_ENCRYPT_HASHED = 0, 1, 2, 3
+PREP_MODES = {"encrypt": VC_PREP_ENCRYPT, "decrypt": VC_PREP_DECRYPT, "hash": VC_PREP_HASH,
+              "encrypt_hashed": VC_PREP_ENCRYPT_HASHED}
+
+
 class Batch:
     """A prepared batch (vc_batch_prepare): launch() only enqueues kernels, so
     it can be captured in a torch.cuda.CUDAGraph (a HIP graph) and replayed.
-    The tensors given here must stay alive as long as the batch."""
+    ``mode`` is "encrypt", "decrypt", "hash" (frame hashes only; ``out`` may
+    be None) or "encrypt_hashed" (hashes already hold H), or a bool (True =
+    decrypt).  The tensors given here must stay alive as long as the batch."""
 
-    def __init__(self, ctx: int, decrypt: bool, frames: Sequence[torch.Tensor], streams: Sequence[int],
-                 seqs: Sequence[int], hashes: torch.Tensor, out: Sequence[torch.Tensor]):
-        for t in list(frames) + list(out):
+    def __init__(self, ctx: int, mode, frames: Sequence[torch.Tensor], streams: Sequence[int],
+                 seqs: Sequence[int], hashes: torch.Tensor, out: Optional[Sequence[torch.Tensor]]):
+        code = (VC_PREP_DECRYPT if mode else VC_PREP_ENCRYPT) if isinstance(mode, bool) else PREP_MODES[mode]
+        out = list(out) if out is not None else []
+        for t in list(frames) + out:
             _check_frame(t)
         if not _hash_buffer_ok(hashes, len(frames)):
-            raise ValueError("hashes must be a CUDA uint8 tensor of count*32 bytes")
-        self._keep = (list(frames), hashes, list(out))
+            raise ValueError("hashes must be a CUDA (or pinned) uint8 tensor of count*32 bytes")
+        self._keep = (list(frames), hashes, out)
         h = C.c_void_p()
-        _check(lib.vc_batch_prepare(C.c_void_p(ctx), 1 if decrypt else 0, len(frames), _ptrs(frames),
-                                    _shapes(frames, streams, seqs), C.c_void_p(hashes.data_ptr()), _ptrs(out),
-                                    C.byref(h)), "vc_batch_prepare")
+        _check(lib.vc_batch_prepare(C.c_void_p(ctx), code, len(frames), _ptrs(frames),
+                                    _shapes(frames, streams, seqs), C.c_void_p(hashes.data_ptr()),
+                                    _ptrs(out) if out else None, C.byref(h)), "vc_batch_prepare")
         self.handle = h.value
 
     def launch(self, stream: Optional[torch.cuda.Stream] = None) -> None:

@@ -347,9 +347,20 @@ def test_documented_errors():
     rc = Vm.lib.encrypt_frames(C.c_void_p(c.ctx), 1, Vm._ptrs([f]), sh, C.c_void_p(H.data_ptr()), Vm._ptrs([out]),
                                None)
     assert rc == Vm.VC_EINVAL
-    # failed calls enqueue nothing: the stream still starts at seq 0
+    # empty calls (count 0, NULL arrays) succeed and enqueue nothing
+    L, ctx = Vm.lib, C.c_void_p(c.ctx)
+    for rc in (L.encrypt_frames(ctx, 0, None, None, None, None, None),
+               L.encrypt_frames_noalloc(ctx, 0, None, None, None, None, None),
+               L.encrypt_frames_hashed(ctx, 0, None, None, None, None, None),
+               L.decrypt_frames(ctx, 0, None, None, None, None, None),
+               L.vc_hash_frames(ctx, 0, None, None, None, None)):
+        assert rc == Vm.VC_OK
+    # neither the failed nor the empty calls moved the chain: the stream
+    # still starts at seq 0 with the key, as in the oracle
     Vm.encrypt_frames(c.ctx, [f], [0], [0], H, [out])
     assert c.status() == 0
+    Cs, Hs, _ = oracle_stream(key_bytes(6), -1.0, 8, [to_np(f)])
+    assert to_np(H)[0].tobytes() == Hs[0] and np.array_equal(to_np(out), Cs[0])
     c.close(); tiny.close()
 
 
