@@ -164,7 +164,6 @@ struct vc_cipher {
     std::vector<hipEvent_t> spare;
     double acc_ms[K_COUNT] = {};
     uint64_t acc_n[K_COUNT] = {};
-    hipStream_t last_stream = nullptr;
     // allocation-free calls (encrypt_frames_noalloc): the device array
     // `scratch` on this context's GPU, a pinned staging buffer for their
     // descriptors, and events that order them with the context's other calls
@@ -875,7 +874,6 @@ int run_call(vc_cipher *ctx, const CallArgs &a) {
         if (e != hipSuccess) return map_err(e);
         ctx->stage_live[slot] = true;
     }
-    ctx->last_stream = s;
     return VC_OK;
 }
 
@@ -1544,7 +1542,6 @@ int vc_batch_launch(vc_batch *b, void *stream) {
     }
     if (e != hipSuccess) return map_err(e);
     for (const auto &kv : b->frames_per_stream) ctx->next_seq[kv.first] += kv.second;
-    ctx->last_stream = s;
     return VC_OK;
 }
 
