@@ -532,8 +532,9 @@ void vc_server_destroy(vc_server *server);
 /* 1 when the kernels can read and write [p, p + bytes) in place: device or
  * managed memory, or pinned host memory that the device addresses at the
  * same address (hipHostMalloc); 0 otherwise (pageable host memory, NULL,
- * bytes == 0, or no device).  The calls above check their hash buffers with
- * it before enqueuing anything.  Host only. */
+ * bytes == 0, or no device).  The first and the last byte are checked, so
+ * the range is expected to lie in one allocation.  The calls above check
+ * their hash buffers with it before enqueuing anything.  Host only. */
 int vc_pointer_reachable(const void *p, size_t bytes);
 
 /* vc_bandwidth_probe: a measurement helper outside the cipher -- the

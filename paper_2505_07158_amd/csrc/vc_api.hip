@@ -179,11 +179,14 @@ struct vc_cipher {
 };
 
 namespace vc {
-// True when [p, p + bytes) is memory the kernels can address as it is:
-// device or managed memory, or pinned host memory mapped at the same
-// address (hipHostMalloc).  Pageable host memory is not (no XNACK), and a
-// kernel touching it faults, so buffers the kernels access in place are
-// checked before anything is enqueued.
+// True when the first and the last byte of [p, p + bytes) lie in memory
+// the kernels can address as it is: device or managed memory, or pinned
+// host memory mapped at the same address (hipHostMalloc).  Pageable host
+// memory is not (no XNACK), and a kernel touching it faults, so buffers the
+// kernels access in place are checked before anything is enqueued.  (A
+// range whose two ends lie in different allocations with unmapped memory
+// between them is not detected: buffers are expected to be one
+// allocation.)
 bool reachable(const void *p, size_t bytes) {
     if (!p || bytes == 0) return false;
     const uint8_t *b = static_cast<const uint8_t *>(p);
