@@ -115,6 +115,35 @@ def test_struct_layouts_match_the_header(tmp_path):
             assert got[(cname, field)] == getattr(py, field).offset, (cname, field)
 
 
+def test_constants_match_the_header(tmp_path):
+    """The binding's status codes, prepared-batch modes and serving kinds
+    have the header's values (a host program built with gcc prints them)."""
+    import shutil
+    import subprocess
+    from paper_2505_07158_amd import serving
+    from paper_2505_07158_amd import vcipher as V
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not found")
+    names = ["VC_OK", "VC_EINVAL", "VC_ENOMEM", "VC_EDEVICE", "VC_EORDER", "VC_ENONFINITE", "VC_EBUSY",
+             "VC_PREP_ENCRYPT", "VC_PREP_DECRYPT", "VC_PREP_HASH", "VC_PREP_ENCRYPT_HASHED"]
+    kinds = ["VC_REQ_ENCRYPT", "VC_REQ_DECRYPT", "VC_BATCH_HASH"]
+    lines = ["#include <stdio.h>", '#include "vcipher.h"', "int main(void) {"]
+    lines += [f'printf("{nm} %d\\n", (int){nm});' for nm in names + kinds]
+    lines += ["return 0;", "}"]
+    src = tmp_path / "consts.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "consts"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict((a, int(b)) for a, b in (ln.split() for ln in subprocess.run(
+        [str(exe)], check=True, capture_output=True, text=True).stdout.splitlines()))
+    for nm in names:
+        assert got[nm] == getattr(V, nm), nm
+    # the serving binding's kind strings are indexed by the header's kinds
+    assert [serving.KINDS[got[k]] for k in kinds] == ["enc", "dec", "hash"]
+    assert V.PREP_MODES == {"encrypt": got["VC_PREP_ENCRYPT"], "decrypt": got["VC_PREP_DECRYPT"],
+                            "hash": got["VC_PREP_HASH"], "encrypt_hashed": got["VC_PREP_ENCRYPT_HASHED"]}
+
+
 def test_pointer_reachable_refuses_host_memory(lib):
     """vc_pointer_reachable: pageable host memory, NULL and empty ranges are
     not device-addressable (with or without a GPU)."""
