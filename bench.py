@@ -859,6 +859,13 @@ def main():
         if cnt:
             kernels_iso[name] = {"avg_us": round(1000.0 * ms / cnt, 1), "launches": cnt}
 
+    # The benchmark's own contexts are done: free their scratch and their
+    # streams before the other legs (each stream holds a share of the
+    # process's hardware queues, and streams that share a queue run in turn).
+    torch.cuda.synchronize()
+    enc.close()
+    dec.close()
+
     # ---- reference: the same work without the pipeline (encrypt_frames,
     # then decrypt_frames on the receiver's stream, double-buffered) ----
     unpiped = None
@@ -1112,11 +1119,6 @@ def main():
                               "per frame; chi2_pass = fraction of channels under 293.25, lse_pass = fraction "
                               "inside (7.901515798, 7.903422936); timings are host wall clock of synchronous "
                               "calls"}
-
-    # The benchmark's own contexts are done; free their scratch before the
-    # other legs.
-    enc.close()
-    dec.close()
 
     # ---- streaming ceiling of this GPU: the library's reference copy and
     # xor kernels (one 16-byte word per thread) over buffers of the size of
