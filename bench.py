@@ -510,7 +510,11 @@ def batched_run(args, steps: int, warmup: int) -> dict:
     el1 = time.perf_counter() - t1
     ok1 = all(torch.equal(p1[i], frames[i]) for i in range(NF))
     same = all(torch.equal(c1[i], c0[i]) for i in range(NF))  # batch 0 of the batched run: same frames and seqs
-    assert enc.status() == 0 and dec.status() == 0
+    assert enc.status() == 0 and dec.status() == 0 and e1.status() == 0 and d1.status() == 0
+    # these contexts are done: free their scratch and streams (hardware-queue
+    # shares) before the graphs run
+    torch.cuda.synchronize()
+    enc.close(); dec.close(); e1.close(); d1.close()
 
     # ---- the same batches as prepared batches (vc_batch_prepare), launched
     # from HIP graphs; every kernel is a launch from a graph (no host work
@@ -662,7 +666,6 @@ def batched_run(args, steps: int, warmup: int) -> dict:
             "cpu_baseline": {"value": round(3 / cpu_s, 3), "unit": "frames/s (encrypt + decrypt)", "cores": 1,
                              "kind": "oracle", "sample": "one frame of each shape (640x480, 1280x720, 1920x1080), "
                              "encrypt + decrypt from the key, single-threaded scalar C oracle", "per_shape": cpu}}
-    enc.close(); dec.close(); e1.close(); d1.close()
     return line
 
 
