@@ -1070,6 +1070,9 @@ def main():
         if k >= 3:
             lat_e.append((b - a) * 1e3)
             lat_d.append((c - b) * 1e3)
+    assert le.status() == 0 and ld.status() == 0
+    le.close()
+    ld.close()
 
     # ---- the plain per-frame path: one call per frame and direction on one
     # stream, queued without host synchronisation ----
