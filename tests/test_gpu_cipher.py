@@ -2,7 +2,8 @@
 oracle on the small workloads (one 64x64 frame for several worker counts;
 a 24-frame 640x480 video), the differential test of Sec. IV-B on the GPU
 path, multi-stream batches (each stream's bytes equal the stream run alone),
-chunked scratch, chain-state export/import and the documented errors."""
+chunked scratch, chain-state export/import, the documented errors, and a
+seeded sweep of random shapes, keys, worker counts and gamma."""
 import numpy as np
 import pytest
 import torch
@@ -490,3 +491,36 @@ def test_hash_buffers_in_pinned_host_memory():
     assert np.array_equal(to_np(Q), video)
     assert c.status() == 0 and d.status() == 0
     c.close(); d.close()
+
+
+def test_random_shapes_keys_and_worker_counts():
+    """A seeded sweep of small frames: random shapes (1..160 x 1..120),
+    random keys, gamma across its range, worker counts from 1 to 1024 (up
+    to the frame's byte count, n = 3wh included) and both confusion forms.
+    Two frames of one stream equal the oracle's (hashes and ciphertext) and
+    decrypt back to the plaintext."""
+    dev = require_gpu()
+    Vm = V()
+    rng = np.random.default_rng(77)
+    for case in range(24):
+        w, h = int(rng.integers(1, 161)), int(rng.integers(1, 121))
+        nmax = min(3 * w * h, 1024)
+        n = [1, nmax, int(rng.integers(1, nmax + 1)), int(rng.integers(1, min(nmax, 64) + 1))][case % 4]
+        gamma = float(rng.uniform(-1.52, -0.06))
+        passes = 2 if case % 3 else 1
+        kb = bytes(rng.integers(0, 256, 32, dtype=np.uint8).tolist())
+        frames = rng.integers(0, 256, (2, h, w, 3), dtype=np.uint8)
+        what = (case, w, h, n, round(gamma, 3), passes)
+        c = Vm.Cipher.from_bytes(kb, gamma, n, scratch_bytes=64 << 20)
+        d = Vm.Cipher.from_bytes(kb, gamma, n, scratch_bytes=64 << 20)
+        c.passes(passes)
+        d.passes(passes)
+        C, H = c.encrypt(to_dev(frames, dev))
+        Cs, Hs, _ = oracle_stream(kb, gamma, n, list(frames))
+        Cn, Hn = to_np(C), to_np(H)
+        for t in range(2):
+            assert Hn[t].tobytes() == Hs[t], what + (t,)
+            assert np.array_equal(Cn[t], Cs[t]), what + (t,)
+        assert torch.equal(d.decrypt(C, H), to_dev(frames, dev)), what
+        assert c.status() == 0 and d.status() == 0, what
+        c.close(); d.close()
