@@ -281,3 +281,103 @@ def test_hash_batches_have_their_own_inflight_limit():
         be.finish_all()
         s.pump()
     assert len(s.completed) == 5 and all(r.hashed for r in s.completed)
+
+
+class CheckingBackend:
+    """A fake backend that checks, at every launch, the scheduler's limits:
+    batches of one kind and class in flight, batch size, one class per
+    batch."""
+
+    def __init__(self, limits, max_batch, cls_of):
+        self.limits, self.max_batch, self.cls_of = limits, max_batch, cls_of
+        self.launched = []   # (kind, [Request], handle)
+
+    def launch(self, kind, reqs):
+        assert 1 <= len(reqs) <= self.max_batch
+        cls = {self.cls_of(r) for r in reqs}
+        assert len(cls) == 1
+        busy = sum(1 for k, rs, h in self.launched if k == kind and self.cls_of(rs[0]) in cls and not h.finished)
+        assert busy < self.limits[kind], (kind, busy)
+        h = FakeHandle()
+        self.launched.append((kind, list(reqs), h))
+        return h
+
+
+hyp = pytest.importorskip("hypothesis")
+st = hyp.strategies
+
+
+@hyp.settings(max_examples=60, deadline=None)
+@hyp.given(budget=st.integers(20, 300), max_inflight=st.integers(1, 3), max_inflight_hash=st.integers(0, 3),
+           max_batch=st.integers(1, 8), hash_first=st.booleans(), max_stream_inflight=st.integers(0, 4),
+           streams=st.integers(1, 5), frames=st.integers(1, 6), classes=st.integers(1, 3),
+           seed=st.integers(0, 10 ** 6))
+def test_scheduler_invariants_over_random_configurations(budget, max_inflight, max_inflight_hash, max_batch,
+                                                         hash_first, max_stream_inflight, streams, frames, classes,
+                                                         seed):
+    """Over random configurations and arrival orders, after every pump: the
+    in-flight bytes are the footprints of the admitted, unfinished requests
+    and stay within the budget unless one request holds them alone; per
+    stream at most max_stream_inflight frames are admitted; at every launch
+    the in-flight batches of that kind and class stay under their limit and
+    a batch holds one class and at most max_batch requests; every request
+    completes exactly once, after its last batch has finished; ordered
+    batches keep each stream's frames in sequence."""
+    rng = random.Random(seed)
+    kinds = {st_: rng.choice(["enc", "dec"]) for st_ in range(streams)}
+    cls_of = lambda r: r.stream % classes
+    limits = {"enc": max_inflight, "dec": max_inflight, "hash": max_inflight_hash or max_inflight}
+    be = CheckingBackend(limits, max_batch, cls_of)
+    s = Scheduler(be.launch, hbm_budget=budget, max_inflight=max_inflight, max_batch=max_batch,
+                  batch_class=cls_of, max_stream_inflight=max_stream_inflight, hash_first=hash_first,
+                  max_inflight_hash=max_inflight_hash)
+    reqs = [req(st_, q, kinds[st_], nbytes=rng.choice([1, 5, 20, 60, budget + 10]))
+            for st_ in range(streams) for q in range(frames)]
+    order = list(reqs)
+    rng.shuffle(order)
+
+    def last_batch(r):
+        return [h for _, rs, h in be.launched if any(x is r for x in rs)][-1]
+
+    seen = [0]
+
+    def check():
+        # requests completed by this pump: their last batch had finished
+        for r in s.completed[seen[0]:]:
+            assert last_batch(r).finished
+        seen[0] = len(s.completed)
+        admitted = [r for r in reqs if r.launched == r.launched and r.done != r.done]
+        assert s.inflight_bytes == sum(r.nbytes for r in admitted)
+        assert s.inflight_bytes <= budget or len(admitted) == 1
+        if max_stream_inflight:
+            per = {}
+            for r in admitted:
+                per[(r.kind, r.stream)] = per.get((r.kind, r.stream), 0) + 1
+            assert all(v <= max_stream_inflight for v in per.values())
+
+    for r in order:
+        s.submit(r)
+        s.pump()
+        check()
+        for _, _, h in be.launched:
+            if rng.random() < 0.5:
+                h.finished = True
+    for _ in range(10 * len(reqs) + 10):
+        if s.idle():
+            break
+        for _, _, h in be.launched:
+            h.finished = True
+        s.pump()
+        check()
+    assert s.idle()
+    assert sorted(id(r) for r in s.completed) == sorted(id(r) for r in reqs)
+    assert all(r.status == 0 for r in reqs)
+    nxt = {}
+    for kind, rs, _ in be.launched:
+        if kind == "hash":
+            continue
+        for r in rs:
+            assert r.seq == nxt.get((kind, r.stream), 0)
+            nxt[(kind, r.stream)] = r.seq + 1
+    hashed = {(r.stream, r.seq) for k, rs, _ in be.launched if k == "hash" for r in rs}
+    assert hashed == ({(r.stream, r.seq) for r in reqs if r.kind == "enc"} if hash_first else set())
