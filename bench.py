@@ -100,6 +100,10 @@ def parse():
     ap.add_argument("--second-n", type=int, default=256, help="worker count of the second row (0 = skip)")
     ap.add_argument("--second-steps", type=int, default=16)
     ap.add_argument("--unpipelined-steps", type=int, default=4, help="steps of the reference without the pipeline")
+    ap.add_argument("--pcie-frames", type=int, default=60,
+                    help="frames per step of the PCIe-inclusive row (0 = skip): frames from and ciphertext to "
+                         "pinned host memory")
+    ap.add_argument("--pcie-steps", type=int, default=6)
     return ap.parse_args()
 
 
@@ -1050,6 +1054,58 @@ def main():
         e2.close()
         d2.close()
 
+    # ---- PCIe-inclusive row (context only, never the value): each step
+    # copies a batch of frames from pinned host memory to the device,
+    # encrypts it and copies the ciphertext back; two buffer sets on two
+    # streams, so that one batch's copies overlap the other's kernels ----
+    pcie = None
+    if args.pcie_frames:
+        NPc = min(args.pcie_frames, T)
+        hin = [torch.empty((NPc, h, w, 3), dtype=torch.uint8, pin_memory=True) for _ in range(2)]
+        hout = [torch.empty((NPc, h, w, 3), dtype=torch.uint8, pin_memory=True) for _ in range(2)]
+        for b_ in range(2):
+            hin[b_].copy_(frames[:NPc])
+        din = [torch.empty((NPc, h, w, 3), dtype=torch.uint8, device=dev) for _ in range(2)]
+        dout = [torch.empty_like(din[0]) for _ in range(2)]
+        hh = [torch.empty((NPc, 32), dtype=torch.uint8, device=dev) for _ in range(2)]
+        s_cp = [torch.cuda.Stream() for _ in range(2)]
+        pc = make_cipher(n, per_frame_scratch * NPc + (64 << 20))
+
+        def pcie_step(j):
+            b_ = j % 2
+            with torch.cuda.stream(s_cp[b_]):
+                din[b_].copy_(hin[b_], non_blocking=True)
+                pc.encrypt(din[b_], out=dout[b_], hashes=hh[b_], stream=s_cp[b_])
+                hout[b_].copy_(dout[b_], non_blocking=True)
+
+        torch.cuda.synchronize()
+        pcie_step(0)
+        torch.cuda.synchronize()
+        # the first batch (frames 0..NPc-1 of the stream, from the key) as
+        # the device-resident path encrypts them
+        ref_c = make_cipher(n, per_frame_scratch * NPc + (64 << 20))
+        ref_out, _ = ref_c.encrypt(frames[:NPc])
+        torch.cuda.synchronize()
+        pcie_ok = bool(torch.equal(hout[0], ref_out.cpu()))
+        ref_c.close()
+        del ref_out
+        pcie_step(1)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for j in range(2, 2 + args.pcie_steps):
+            pcie_step(j)
+        torch.cuda.synchronize()
+        el_p = time.perf_counter() - a
+        assert pc.status() == 0
+        pc.close()
+        moved = 2.0 * NPc * L * args.pcie_steps
+        pcie = {"value": round(NPc * args.pcie_steps / el_p, 1), "unit": "frames/s (encrypt only)",
+                "frames_per_step": NPc, "steps": args.pcie_steps, "pcie_GBps": round(moved / el_p / 1e9, 1),
+                "bytes_per_frame_over_pcie": 2 * L, "first_batch_equals_device_path": pcie_ok,
+                "mode": "per step: frames copied from pinned host memory, encrypt_frames, ciphertext copied back "
+                        "to pinned host memory; two buffer sets on two streams; context only, not the value"}
+        del hin, hout, din, dout, hh
+
     # ---- single-frame latency (encrypt, then decrypt, one 1080p frame) ----
     lat_e, lat_d = [], []
     le = make_cipher(n, max(4 * per_frame_scratch, 64 << 20))
@@ -1267,6 +1323,7 @@ def main():
                         "decrypt_p50": round(pct(lat_d, 50), 3), "decrypt_p99": round(pct(lat_d, 99), 3),
                         "mode": f"one {w}x{h} frame per call, host-synchronised"} if lat_e else None),
         "second_row": second,
+        "pcie_row": pcie,
         "unpipelined": unpiped,
         "plain_per_frame": plain_pf,
         "statistics": statistics,
